@@ -1,0 +1,77 @@
+"""CPU oracle for connected-components labelling — TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library and its Python binding never import
+it; the two share no code.
+
+``oracle_label(img, connectivity)`` returns the canonical labelling of a
+binary image, as defined in the paper's problem statement (Section 3, first
+paragraph: pixel position P(x, y) = x + y * W, foreground I = 1): background
+pixels get 0, a foreground pixel gets 1 + the smallest position in its
+4- or 8-connected component.  The arithmetic lives in ``ccl_oracle.c`` (a
+plain two-pass union-find); this module only loads it and marshals numpy
+arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ccl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-Wall", "-Wextra",
+             "-o", tmp, _SRC],
+            check=True,
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_label.restype = ctypes.c_int
+        lib.oracle_label.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_int32, ctypes.c_void_p,
+        ]
+        _lib = lib
+    return _lib
+
+
+def oracle_label(img: np.ndarray, connectivity: int = 8) -> np.ndarray:
+    """Canonical labels of a 2-D uint8 image (nonzero = foreground).
+
+    ``img`` may be a strided view whose rows are contiguous; the row pitch in
+    bytes is taken from its first stride.  Returns a dense int32 H x W array.
+    """
+    if img.ndim != 2 or img.dtype != np.uint8:
+        raise ValueError("oracle_label expects a 2-D uint8 array")
+    H, W = img.shape
+    out = np.zeros((H, W), dtype=np.int32)
+    if H == 0 or W == 0:
+        return out
+    if img.strides[1] != 1 or img.strides[0] < W:
+        img = np.ascontiguousarray(img)
+    pitch = img.strides[0]
+    rc = _load().oracle_label(img.ctypes.data, H, W, pitch, int(connectivity),
+                              out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_label failed with status {rc}")
+    return out
