@@ -1,0 +1,135 @@
+/*
+ * ccl.h — C ABI of the MI355X (gfx950) connected-components labeller.
+ *
+ * Method: the block-based coarse-to-fine labelling of Chen et al., "Efficient
+ * Parallel Connected Components Labeling with a Coarse-to-fine Strategy"
+ * (arXiv 1712.09789), Section 3: (1) local labelling of each image tile
+ * (initialisation, row-column connection, label-equivalence unification,
+ * refinement, ID conversion; Algorithm "Local labeling with coarse-to-fine
+ * strategy" and Section 3.1), (2) block merge that inspects only pixels on
+ * tile borders (Algorithm "Boundary analysis", Section 3.2, Eq. 1-2), and
+ * (3) the global root-find that writes the final label map (Section 3.3).
+ *
+ * Output convention (all entry points): labels[y * W + x] is 0 for a
+ * background pixel and, for a foreground pixel, 1 + the smallest raster
+ * position y' * W + x' of its connected component.  The paper's labels are
+ * exactly these root positions (Section 3.1.1: the provisional label of a
+ * pixel is its position and the root of a list is the element whose label is
+ * its own address; Sections 3.1.3 and 3.2: the larger root always points at
+ * the smaller); the "+1" reserves 0 for background.  The result is therefore
+ * unique and does not depend on tile shape, batch composition or timing.
+ *
+ * Input convention: the image is uint8, H rows of W pixels, row y starting
+ * at img + y * pitch_bytes.  A pixel is foreground when its byte is nonzero
+ * (the paper's binary intensity I(x, y) in {0, 1}, Section 3).  Bytes between
+ * W and pitch_bytes are never read.
+ *
+ * Pointers named img/labels are DEVICE pointers on the current HIP device.
+ * `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ * enqueued on `stream` and the call returns without waiting; the labels are
+ * valid once the stream has reached that point.  Argument errors are detected
+ * on the host before anything is enqueued, and `labels` is then untouched.
+ *
+ * The library owns a per-(device, stream) workspace cache that grows on
+ * demand (hipMalloc); concurrent calls on DIFFERENT streams use different
+ * workspaces and may overlap freely.  Calls on the same stream are ordered
+ * by the stream.
+ */
+#ifndef CCL_H
+#define CCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CCL_OK = 0,
+    CCL_ERR_INVALID_ARG = -1, /* null pointer, negative size, pitch < W,
+                                 connectivity not 4/8, img and labels overlap */
+    CCL_ERR_TOO_LARGE = -2,   /* H * W > 2^31 - 1 (labels are int32)         */
+    CCL_ERR_OUT_OF_MEMORY = -3, /* the workspace could not grow              */
+    CCL_ERR_HIP = -4          /* a HIP call or kernel launch failed           */
+} ccl_status;
+
+/*
+ * Label one image (Section 3, all three steps).
+ *   img          device, uint8, H rows, row stride pitch_bytes (>= W);
+ *                caller-owned, only read.
+ *   H, W         image size in pixels; H == 0 or W == 0 is a no-op.
+ *   connectivity 4 (the paper's setting, Section 4.2) or 8.
+ *   labels       device, int32, dense H * W (row stride W); caller-owned,
+ *                fully overwritten.  Must not overlap img.
+ * Returns a ccl_status; on error ccl_last_error() holds a message.
+ */
+int ccl_label(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+              int32_t connectivity, int32_t* labels, void* stream);
+
+/* One image of a batch; same meaning as the ccl_label arguments. */
+typedef struct {
+    const uint8_t* img;
+    int32_t H;
+    int32_t W;
+    int64_t pitch_bytes;
+    int32_t connectivity;
+    int32_t* labels;
+} ccl_image_desc;
+
+/*
+ * Label n independent images (the same three steps per image).
+ *   descs   HOST array of n descriptors, read during the call only.
+ *   n       number of images; 0 is a no-op.
+ * Every descriptor is validated before anything is enqueued; the first bad
+ * one fails the whole call (its index is in ccl_last_error()).  Outputs are
+ * identical to labelling each image alone with ccl_label.
+ */
+int ccl_label_batch(const ccl_image_desc* descs, int32_t n, void* stream);
+
+/*
+ * Debugging aid for the local step alone (Section 3.1): every tile is
+ * labelled as if it were a separate image, and each foreground pixel gets
+ * 1 + the raster position (in the whole image) of the smallest pixel of its
+ * component INSIDE its tile.  Tiles are tile_cols() wide and tile_rows()
+ * high, aligned at (0, 0).  Same arguments and errors as ccl_label.
+ */
+int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                    int32_t connectivity, int32_t* labels, void* stream);
+
+/* Tile shape used by the local step (pixels). */
+int32_t ccl_tile_cols(void);
+int32_t ccl_tile_rows(void);
+
+/* Workspace bytes one ccl_label call of this size needs (0 for an empty
+   image, -1 for invalid sizes). */
+int64_t ccl_workspace_bytes(int32_t H, int32_t W);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char* ccl_last_error(void);
+
+/* Free every cached workspace of `device` (synchronises that device). */
+int ccl_release_workspace(int32_t device);
+
+/*
+ * Per-kernel timing with HIP events recorded on the launch stream.
+ * ccl_timing_enable(1) clears the counters and starts recording around every
+ * kernel the library launches; ccl_timing_read() waits for the recorded
+ * events and fills, for each kernel kind k < n (0 = local, 1 = seam,
+ * 2 = final, 3 = copy), the summed milliseconds ms[k] and launch count
+ * launches[k].  Returns the number of kinds (4).
+ */
+int ccl_timing_enable(int32_t enable);
+int ccl_timing_read(double* ms, int64_t* launches, int32_t n);
+
+/*
+ * Plain device-to-device copy of `bytes` bytes (both device pointers,
+ * 16-byte aligned, non-overlapping) by a streaming kernel.  Used only to
+ * calibrate bandwidth figures and hardware byte counters.
+ */
+int ccl_copy_bytes(const void* src, void* dst, int64_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCL_H */

@@ -1,0 +1,182 @@
+"""Python binding of the C ABI in include/ccl.h (argument marshalling only).
+
+Every labelling step runs in the HIP kernels of ``libccl.so``; this module
+passes device pointers, sizes and the stream handle, and turns status codes
+into exceptions.  torch is used for device memory and streams only.  There is
+no fallback: if the library is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccl.so")
+
+CCL_OK = 0
+STATUS_NAMES = {0: "CCL_OK", -1: "CCL_ERR_INVALID_ARG", -2: "CCL_ERR_TOO_LARGE",
+                -3: "CCL_ERR_OUT_OF_MEMORY", -4: "CCL_ERR_HIP"}
+KERNEL_KINDS = ("local", "seam", "final", "copy")
+
+
+class CCLError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("pitch_bytes", ctypes.c_int64), ("connectivity", ctypes.c_int32),
+                ("labels", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run "
+                          "`python -m paper_1712_09789_amd.build` first")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    for name in ("ccl_label", "ccl_label_local"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [vp, i32, i32, i64, i32, vp, vp]
+    lib.ccl_label_batch.restype = ctypes.c_int
+    lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), i32, vp]
+    lib.ccl_tile_cols.restype = i32
+    lib.ccl_tile_rows.restype = i32
+    lib.ccl_workspace_bytes.restype = i64
+    lib.ccl_workspace_bytes.argtypes = [i32, i32]
+    lib.ccl_last_error.restype = ctypes.c_char_p
+    lib.ccl_release_workspace.restype = ctypes.c_int
+    lib.ccl_release_workspace.argtypes = [i32]
+    lib.ccl_timing_enable.restype = ctypes.c_int
+    lib.ccl_timing_enable.argtypes = [i32]
+    lib.ccl_timing_read.restype = ctypes.c_int
+    lib.ccl_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), i32]
+    lib.ccl_copy_bytes.restype = ctypes.c_int
+    lib.ccl_copy_bytes.argtypes = [vp, vp, i64, vp]
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != CCL_OK:
+        raise CCLError(status, _lib.ccl_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _image_args(img: torch.Tensor):
+    if img.dim() != 2 or img.dtype != torch.uint8:
+        raise ValueError("image must be a 2-D torch.uint8 tensor")
+    if not img.is_cuda:
+        raise ValueError("image must be a device (cuda) tensor")
+    H, W = img.shape
+    if H > 0 and W > 1 and img.stride(1) != 1:
+        raise ValueError("image rows must be contiguous (stride(1) == 1)")
+    pitch = img.stride(0) if H > 1 else W
+    return H, W, max(pitch, W)
+
+
+def _out_for(img: torch.Tensor, out: torch.Tensor | None) -> torch.Tensor:
+    H, W = img.shape
+    if out is None:
+        return torch.empty((H, W), dtype=torch.int32, device=img.device)
+    if out.shape != (H, W) or out.dtype != torch.int32 or not out.is_contiguous() \
+            or out.device != img.device:
+        raise ValueError("out must be a contiguous int32 tensor of the image's shape "
+                         "on the image's device")
+    return out
+
+
+def label(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | None = None,
+          stream=None) -> torch.Tensor:
+    """Canonical connected-component labels of a uint8 device image
+    (0 = background, else 1 + smallest raster position of the component)."""
+    H, W, pitch = _image_args(img)
+    out = _out_for(img, out)
+    _check(_lib.ccl_label(img.data_ptr(), H, W, pitch, int(connectivity), out.data_ptr(),
+                          _stream_handle(stream)))
+    return out
+
+
+def label_local(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """Local step only: every tile labelled as a separate image."""
+    H, W, pitch = _image_args(img)
+    out = _out_for(img, out)
+    _check(_lib.ccl_label_local(img.data_ptr(), H, W, pitch, int(connectivity),
+                                out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def make_descs(imgs: Sequence[torch.Tensor], outs: Sequence[torch.Tensor],
+               connectivity) -> ctypes.Array:
+    n = len(imgs)
+    conns = connectivity if isinstance(connectivity, (list, tuple)) else [connectivity] * n
+    arr = (ImageDesc * max(n, 1))()
+    for i, (im, o) in enumerate(zip(imgs, outs)):
+        H, W, pitch = _image_args(im)
+        arr[i] = ImageDesc(im.data_ptr(), H, W, pitch, int(conns[i]), o.data_ptr())
+    return arr
+
+
+def label_batch(imgs: Sequence[torch.Tensor], connectivity=8,
+                outs: Sequence[torch.Tensor] | None = None, stream=None):
+    """Label several independent images in one call; returns the label tensors."""
+    if outs is None:
+        outs = [_out_for(im, None) for im in imgs]
+    else:
+        outs = [_out_for(im, o) for im, o in zip(imgs, outs)]
+    descs = make_descs(imgs, outs, connectivity)
+    _check(_lib.ccl_label_batch(descs, len(imgs), _stream_handle(stream)))
+    return list(outs)
+
+
+def tile_shape() -> tuple[int, int]:
+    """(rows, cols) of the local step's tiles."""
+    return int(_lib.ccl_tile_rows()), int(_lib.ccl_tile_cols())
+
+
+def workspace_bytes(H: int, W: int) -> int:
+    return int(_lib.ccl_workspace_bytes(H, W))
+
+
+def release_workspace(device: int = 0) -> None:
+    _check(_lib.ccl_release_workspace(device))
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(_lib.ccl_timing_enable(1 if on else 0))
+
+
+def timing_read() -> dict:
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    k = _lib.ccl_timing_read(ms, n, 4)
+    if k < 0:
+        _check(k)
+    return {KERNEL_KINDS[i]: (float(ms[i]), int(n[i])) for i in range(4)}
+
+
+def copy_bytes(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    _check(_lib.ccl_copy_bytes(src.data_ptr(), dst.data_ptr(), nbytes,
+                               _stream_handle(stream)))

@@ -1,0 +1,326 @@
+// Host side of the C ABI declared in include/ccl.h: argument validation,
+// the per-(device, stream) workspace cache, and the optional event timer.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ccl.h"
+#include "ccl_kernels.h"
+
+namespace ccl {
+
+static thread_local std::string g_err;
+
+static int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int status, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// workspace cache: one grow-only buffer per (device, stream)
+// ---------------------------------------------------------------------------
+
+struct WsEntry {
+    void* ptr = nullptr;
+    int64_t bytes = 0;
+};
+
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
+
+static int get_workspace(int64_t need, hipStream_t st, void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsEntry& w = g_ws[{dev, st}];
+    if (w.bytes < need) {
+        if (w.ptr) {
+            // earlier work on this stream may still read the old buffer
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess)
+                return fail(CCL_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        int64_t grow = need + need / 4;
+        e = hipMalloc(&w.ptr, (size_t)grow);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            w.ptr = nullptr;
+            e = hipMalloc(&w.ptr, (size_t)need);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                w.ptr = nullptr;
+                return fail(CCL_ERR_OUT_OF_MEMORY, "workspace of %lld bytes: %s",
+                            (long long)need, hipGetErrorString(e));
+            }
+            grow = need;
+        }
+        w.bytes = grow;
+    }
+    *out = w.ptr;
+    return CCL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// event timer
+// ---------------------------------------------------------------------------
+
+struct KernelTimer {
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::mutex mu;
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> done;
+    hipEvent_t open[NKINDS] = {};
+    double ms[NKINDS] = {};
+    int64_t launches[NKINDS] = {};
+
+    hipEvent_t take()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+static KernelTimer g_timer;
+static bool g_timing = false;
+
+void timer_begin(KernelTimer* t, int kind, hipStream_t st)
+{
+    if (!t) return;
+    std::lock_guard<std::mutex> lk(t->mu);
+    hipEvent_t e = t->take();
+    if (e && hipEventRecord(e, st) == hipSuccess) t->open[kind] = e;
+}
+
+void timer_end(KernelTimer* t, int kind, hipStream_t st)
+{
+    if (!t) return;
+    std::lock_guard<std::mutex> lk(t->mu);
+    hipEvent_t a = t->open[kind];
+    t->open[kind] = nullptr;
+    if (!a) return;
+    hipEvent_t b = t->take();
+    if (b && hipEventRecord(b, st) == hipSuccess) t->done.push_back({kind, a, b});
+}
+
+static KernelTimer* active_timer() { return g_timing ? &g_timer : nullptr; }
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+
+static int validate(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, int32_t conn,
+                    const int32_t* labels, const char* who)
+{
+    if (H < 0 || W < 0) return fail(CCL_ERR_INVALID_ARG, "%s: negative size %dx%d", who, H, W);
+    if (conn != 4 && conn != 8)
+        return fail(CCL_ERR_INVALID_ARG, "%s: connectivity %d is not 4 or 8", who, conn);
+    if (H == 0 || W == 0) return CCL_OK;
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX)
+        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%d pixels exceed int32 labels", who, H, W);
+    if (!img || !labels) return fail(CCL_ERR_INVALID_ARG, "%s: null pointer", who);
+    if (pitch < W)
+        return fail(CCL_ERR_INVALID_ARG, "%s: pitch %lld < width %d", who, (long long)pitch, W);
+    const int64_t ntiles = (int64_t)((W + TW - 1) / TW) * ((H + TILE_ROWS - 1) / TILE_ROWS);
+    if (ntiles * NSLOTS > (int64_t)INT32_MAX)
+        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%d needs too many tiles", who, H, W);
+    const uintptr_t i0 = (uintptr_t)img, i1 = i0 + (uintptr_t)((int64_t)(H - 1) * pitch + W);
+    const uintptr_t l0 = (uintptr_t)labels, l1 = l0 + (uintptr_t)((int64_t)H * W * 4);
+    if (i0 < l1 && l0 < i1) return fail(CCL_ERR_INVALID_ARG, "%s: img and labels overlap", who);
+    return CCL_OK;
+}
+
+static ImageArgs make_args(const uint8_t* img, int32_t H, int32_t W, int64_t pitch,
+                           int32_t conn, int32_t* labels)
+{
+    ImageArgs a;
+    a.img = img;
+    a.pitch = pitch;
+    a.labels = labels;
+    a.H = H;
+    a.W = W;
+    a.ntx = (W + TW - 1) / TW;
+    a.nty = (H + TILE_ROWS - 1) / TILE_ROWS;
+    a.conn = conn;
+    a.vec_in = ((uintptr_t)img % 16 == 0) && (pitch % 16 == 0);
+    a.vec_out = ((uintptr_t)labels % 16 == 0) && (W % 4 == 0);
+    return a;
+}
+
+static int label_one(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, int32_t conn,
+                     int32_t* labels, hipStream_t st, bool local_only, const char* who)
+{
+    int rc = validate(img, H, W, pitch, conn, labels, who);
+    if (rc != CCL_OK || H == 0 || W == 0) return rc;
+    ImageArgs a = make_args(img, H, W, pitch, conn, labels);
+    const int64_t ntiles = (int64_t)a.ntx * a.nty;
+    void* base = nullptr;
+    rc = get_workspace(workspace_bytes(ntiles), st, &base);
+    if (rc != CCL_OK) return rc;
+    hipError_t e = launch_label(a, carve_workspace(base, ntiles), st, active_timer(), local_only);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return CCL_OK;
+}
+
+}  // namespace ccl
+
+using namespace ccl;
+
+extern "C" {
+
+int ccl_label(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+              int32_t connectivity, int32_t* labels, void* stream)
+{
+    g_err.clear();
+    return label_one(img, H, W, pitch_bytes, connectivity, labels,
+                     static_cast<hipStream_t>(stream), false, "ccl_label");
+}
+
+int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                    int32_t connectivity, int32_t* labels, void* stream)
+{
+    g_err.clear();
+    return label_one(img, H, W, pitch_bytes, connectivity, labels,
+                     static_cast<hipStream_t>(stream), true, "ccl_label_local");
+}
+
+int ccl_label_batch(const ccl_image_desc* descs, int32_t n, void* stream)
+{
+    g_err.clear();
+    if (n < 0) return fail(CCL_ERR_INVALID_ARG, "ccl_label_batch: n = %d", n);
+    if (n == 0) return CCL_OK;
+    if (!descs) return fail(CCL_ERR_INVALID_ARG, "ccl_label_batch: null descriptor array");
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        char who[64];
+        snprintf(who, sizeof who, "ccl_label_batch[%d]", i);
+        int rc = validate(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels, who);
+        if (rc != CCL_OK) return rc;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        int rc = label_one(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels,
+                           static_cast<hipStream_t>(stream), false, "ccl_label_batch");
+        if (rc != CCL_OK) return rc;
+    }
+    return CCL_OK;
+}
+
+int32_t ccl_tile_cols(void) { return TW; }
+int32_t ccl_tile_rows(void) { return TILE_ROWS; }
+
+int64_t ccl_workspace_bytes(int32_t H, int32_t W)
+{
+    if (H < 0 || W < 0) return -1;
+    if (H == 0 || W == 0) return 0;
+    const int64_t ntiles = (int64_t)((W + TW - 1) / TW) * ((H + TILE_ROWS - 1) / TILE_ROWS);
+    return workspace_bytes(ntiles);
+}
+
+const char* ccl_last_error(void) { return g_err.c_str(); }
+
+int ccl_release_workspace(int32_t device)
+{
+    g_err.clear();
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    bool any = false;
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        if (it->first.first == device) {
+            if (!any) {
+                if ((e = hipSetDevice(device)) != hipSuccess)
+                    return fail(CCL_ERR_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+                (void)hipDeviceSynchronize();
+                any = true;
+            }
+            if (it->second.ptr) (void)hipFree(it->second.ptr);
+            it = g_ws.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    if (any) (void)hipSetDevice(prev);
+    return CCL_OK;
+}
+
+int ccl_timing_enable(int32_t enable)
+{
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    for (auto& r : g_timer.done) {
+        g_timer.pool.push_back(r.a);
+        g_timer.pool.push_back(r.b);
+    }
+    g_timer.done.clear();
+    for (int k = 0; k < NKINDS; ++k) {
+        g_timer.ms[k] = 0.0;
+        g_timer.launches[k] = 0;
+    }
+    g_timing = enable != 0;
+    return CCL_OK;
+}
+
+int ccl_timing_read(double* ms, int64_t* launches, int32_t n)
+{
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    for (auto& r : g_timer.done) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess) return fail(CCL_ERR_HIP, "timing: %s", hipGetErrorString(e));
+        g_timer.ms[r.kind] += t;
+        g_timer.launches[r.kind] += 1;
+        g_timer.pool.push_back(r.a);
+        g_timer.pool.push_back(r.b);
+    }
+    g_timer.done.clear();
+    for (int k = 0; k < n && k < NKINDS; ++k) {
+        if (ms) ms[k] = g_timer.ms[k];
+        if (launches) launches[k] = g_timer.launches[k];
+    }
+    return NKINDS;
+}
+
+int ccl_copy_bytes(const void* src, void* dst, int64_t bytes, void* stream)
+{
+    g_err.clear();
+    if (bytes < 0 || (bytes > 0 && (!src || !dst)))
+        return fail(CCL_ERR_INVALID_ARG, "ccl_copy_bytes: bad arguments");
+    if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)bytes) % 16)
+        return fail(CCL_ERR_INVALID_ARG, "ccl_copy_bytes: pointers and size must be 16-byte aligned");
+    if (bytes == 0) return CCL_OK;
+    hipError_t e = launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream), active_timer());
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "ccl_copy_bytes: %s", hipGetErrorString(e));
+    return CCL_OK;
+}
+
+}  // extern "C"

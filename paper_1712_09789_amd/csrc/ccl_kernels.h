@@ -1,0 +1,67 @@
+// Internal interface between the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccl {
+
+// Tile width: one 64-bit foreground mask per tile row, one wavefront lane per
+// row in the local kernels.
+constexpr int TW = 64;
+
+#ifndef CCL_TILE_ROWS
+#define CCL_TILE_ROWS 64
+#endif
+constexpr int TILE_ROWS = CCL_TILE_ROWS;
+constexpr int NSLOTS = 2 * TW + 2 * TILE_ROWS;  // border pixels per tile
+
+struct ImageArgs {
+    const uint8_t* img;
+    int64_t pitch;    // bytes between rows of img
+    int32_t* labels;  // dense H x W
+    int32_t H, W;
+    int32_t ntx, nty;  // tile grid
+    int32_t conn;      // 4 or 8
+    int32_t vec_in;    // img and pitch are 16-byte aligned
+    int32_t vec_out;   // labels rows are 16-byte aligned (W % 4 == 0)
+};
+
+// Device workspace of one image.
+struct Workspace {
+    uint64_t* bits;    // [ntiles][TILE_ROWS] foreground masks
+    int32_t* slots;    // [ntiles][NSLOTS] forest node of each border pixel, -1 = bg
+    uint64_t* forest;  // [ntiles][NSLOTS] (key of parent << 32) | parent node
+};
+
+inline int64_t workspace_bytes(int64_t ntiles)
+{
+    auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    return up(ntiles * TILE_ROWS * 8) + up(ntiles * NSLOTS * 4) + up(ntiles * NSLOTS * 8);
+}
+
+inline Workspace carve_workspace(void* base, int64_t ntiles)
+{
+    auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    char* p = static_cast<char*>(base);
+    Workspace ws;
+    ws.bits = reinterpret_cast<uint64_t*>(p);
+    p += up(ntiles * TILE_ROWS * 8);
+    ws.slots = reinterpret_cast<int32_t*>(p);
+    p += up(ntiles * NSLOTS * 4);
+    ws.forest = reinterpret_cast<uint64_t*>(p);
+    return ws;
+}
+
+enum { KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, NKINDS = 4 };
+
+struct KernelTimer;  // host-side event recorder, null when timing is off
+void timer_begin(KernelTimer* t, int kind, hipStream_t st);
+void timer_end(KernelTimer* t, int kind, hipStream_t st);
+
+hipError_t launch_label(const ImageArgs& a, const Workspace& ws, hipStream_t st,
+                        KernelTimer* timer, bool local_only);
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,
+                       KernelTimer* timer);
+
+}  // namespace ccl

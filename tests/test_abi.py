@@ -1,0 +1,108 @@
+"""The C-ABI library loads on the CPU, exports every function declared in
+include/ccl.h, and rejects bad arguments on the host before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccl.h")
+LIB = os.path.join(ROOT, "paper_1712_09789_amd", "libccl.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(ccl_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libccl.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ccl_label", "ccl_label_batch", "ccl_last_error",
+                     "ccl_release_workspace"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _label(lib, name="ccl_label"):
+    f = getattr(lib, name)
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.ccl_last_error.restype = ctypes.c_char_p
+    return f
+
+
+FAKE_IMG = 0x10000000
+FAKE_OUT = 0x20000000
+
+
+@pytest.mark.parametrize("name", ["ccl_label", "ccl_label_local"])
+@pytest.mark.parametrize("args,status", [
+    ((FAKE_IMG, -1, 4, 4, 8, FAKE_OUT), -1),       # negative height
+    ((FAKE_IMG, 4, -4, 4, 8, FAKE_OUT), -1),       # negative width
+    ((FAKE_IMG, 4, 4, 4, 6, FAKE_OUT), -1),        # connectivity 6
+    ((None, 4, 4, 4, 8, FAKE_OUT), -1),            # null image
+    ((FAKE_IMG, 4, 4, 4, 8, None), -1),            # null labels
+    ((FAKE_IMG, 4, 8, 7, 8, FAKE_OUT), -1),        # pitch < W
+    ((FAKE_IMG, 4, 4, 4, 8, FAKE_IMG + 8), -1),    # overlap
+    ((FAKE_IMG, 65536, 65536, 65536, 8, FAKE_OUT), -2),  # > 2^31 - 1 pixels
+    ((None, 0, 5, 5, 8, None), 0),                 # empty image: no-op
+    ((None, 5, 0, 0, 4, None), 0),
+])
+def test_validation(lib, name, args, status):
+    f = _label(lib, name)
+    assert f(*args, None) == status
+    if status != 0:
+        assert len(lib.ccl_last_error()) > 0
+
+
+def test_batch_validation(lib):
+    import paper_1712_09789_amd.ccl as c  # the binding loads on CPU too
+    descs = (c.ImageDesc * 3)()
+    descs[0] = c.ImageDesc(FAKE_IMG, 4, 4, 4, 8, FAKE_OUT)
+    descs[1] = c.ImageDesc(FAKE_IMG + 4096, 4, 4, 4, 5, FAKE_OUT + 4096)
+    descs[2] = c.ImageDesc(FAKE_IMG + 8192, 4, 4, 4, 8, FAKE_OUT + 8192)
+    assert c.lib().ccl_label_batch(descs, 3, None) == -1
+    assert b"[1]" in c.lib().ccl_last_error()
+    assert c.lib().ccl_label_batch(descs, 0, None) == 0
+    assert c.lib().ccl_label_batch(None, 2, None) == -1
+
+
+def test_sizes_and_shape(lib):
+    import paper_1712_09789_amd.ccl as c
+    rows, cols = c.tile_shape()
+    assert cols == 64 and rows in (16, 32, 64, 128, 256)
+    assert c.workspace_bytes(0, 10) == 0
+    assert c.workspace_bytes(-1, 10) == -1
+    assert c.workspace_bytes(8192, 8192) > 0
+
+
+def test_copy_validation(lib):
+    import paper_1712_09789_amd.ccl as c
+    assert c.lib().ccl_copy_bytes(FAKE_IMG, FAKE_OUT, 15, None) == -1
+    assert c.lib().ccl_copy_bytes(FAKE_IMG + 1, FAKE_OUT, 16, None) == -1
+    assert c.lib().ccl_copy_bytes(None, None, 0, None) == 0
+
+
+def test_product_path_does_not_touch_the_oracle():
+    # the library sources and the binding never import, load or include it
+    pkg = os.path.join(ROOT, "paper_1712_09789_amd")
+    bad = re.compile(r"(import\s+oracle|from\s+oracle|liboracle|ccl_oracle|oracle_label)")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert not bad.search(text), fn

@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Labels are canonical (1 + smallest raster position of the component, 0 for
+background), so the comparison is element-by-element equality: tolerance 0.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import oracle_label
+from paper_1712_09789_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ccl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1712_09789_amd.ccl as c
+    return c
+
+
+def to_dev(img):
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def gpu_label(ccl, img, conn):
+    out = ccl.label(to_dev(img), conn)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_parity(ccl, img, conn, what=""):
+    print(f"[parity] {what} {img.shape} conn={conn}", flush=True)
+    got = gpu_label(ccl, img, conn)
+    want = oracle_label(img, conn)
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        y, x = bad[0]
+        raise AssertionError(f"{what} {img.shape} conn={conn}: {len(bad)} mismatches, "
+                             f"first at ({y},{x}) got {got[y, x]} want {want[y, x]}")
+
+
+@functools.lru_cache(maxsize=None)
+def cached(kind, H, W, seed, items=()):
+    return wl.make(kind, H, W, seed=seed, **dict(items))
+
+
+# --- small and ragged ------------------------------------------------------
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 64), (64, 1), (3, 5), (63, 65), (64, 64),
+                                 (65, 63), (1, 300), (300, 1), (127, 129), (200, 333)])
+@pytest.mark.parametrize("p", [0.3, 0.5, 0.7])
+def test_small_random(ccl, H, W, p, conn):
+    assert_parity(ccl, wl.bernoulli(H, W, p, seed=H * 1000 + W), conn, f"bernoulli{p}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("kind,kw", [("full", {}), ("empty", {}), ("checkerboard", {}),
+                                     ("stripes", {"period": 2}), ("spiral", {}),
+                                     ("serpentine", {"width": 1}),
+                                     ("serpentine", {"width": 3}),
+                                     ("serpentine", {"width": 1, "vertical": True}),
+                                     ("serpentine", {"width": 2, "vertical": True})])
+@pytest.mark.parametrize("H,W", [(130, 190), (256, 256), (301, 517)])
+def test_geometries(ccl, kind, kw, H, W, conn):
+    assert_parity(ccl, wl.make(kind, H, W, **kw), conn, kind)
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_seam_patterns(ccl, conn):
+    """Random 4x4 patterns centred on every kind of seam position: a vertical
+    seam, a horizontal seam and a four-tile corner, in one image per trial."""
+    rows, cols = ccl.tile_shape()
+    rng = np.random.default_rng(conn)
+    H, W = 3 * rows, 3 * cols
+    for trial in range(40):
+        img = np.zeros((H, W), np.uint8)
+        for cy, cx in [(rows // 2, cols), (rows, cols // 2), (rows, cols),
+                       (2 * rows, 2 * cols), (rows, 2 * cols), (2 * rows, cols)]:
+            img[cy - 2:cy + 2, cx - 2:cx + 2] = rng.random((4, 4)) < 0.5
+        assert_parity(ccl, img, conn, f"seam trial {trial}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_values_pitch_alignment(ccl, conn):
+    img = wl.bernoulli(150, 200, 0.5, seed=11)
+    want = oracle_label(img, conn)
+    rng = np.random.default_rng(0)
+    # any nonzero byte is foreground
+    for enc in (255, None):
+        v = img * (np.uint8(enc) if enc else rng.integers(1, 256, img.shape, dtype=np.uint8))
+        assert np.array_equal(gpu_label(ccl, v.astype(np.uint8), conn), want)
+    # padded rows with junk past W (pitch 256, aligned path)
+    pad = np.full((150, 256), 3, np.uint8)
+    pad[:, :200] = img
+    t = to_dev(pad)[:, :200]
+    out = ccl.label(t, conn)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    # unaligned start and odd pitch (byte path)
+    pad2 = np.full((150, 203), 5, np.uint8)
+    pad2[:, 1:201] = img
+    t2 = to_dev(pad2)[:, 1:201]
+    out2 = ccl.label(t2, conn)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), want)
+    # width not a multiple of 4 (scalar label stores)
+    img3 = wl.bernoulli(77, 203, 0.5, seed=12)
+    assert_parity(ccl, img3, conn, "W%4!=0")
+
+
+def test_empty_shapes(ccl):
+    for H, W in [(0, 0), (0, 7), (7, 0)]:
+        t = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+        out = ccl.label(t, 8)
+        torch.cuda.synchronize()
+        assert out.shape == (H, W)
+
+
+def test_errors_leave_output_untouched(ccl):
+    t = torch.ones((8, 8), dtype=torch.uint8, device="cuda")
+    out = torch.full((8, 8), -7, dtype=torch.int32, device="cuda")
+    with pytest.raises(ccl.CCLError):
+        ccl.label(t, 6, out=out)
+    torch.cuda.synchronize()
+    assert bool((out == -7).all())
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_local_step_matches_tilewise_oracle(ccl, conn):
+    rows, cols = ccl.tile_shape()
+    img = wl.bernoulli(2 * rows + 17, 3 * cols + 9, 0.55, seed=5)
+    t = to_dev(img)
+    got = ccl.label_local(t, conn)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    H, W = img.shape
+    for y0 in range(0, H, rows):
+        for x0 in range(0, W, cols):
+            tile = img[y0:y0 + rows, x0:x0 + cols]
+            th, tw = tile.shape
+            loc = oracle_label(tile, conn).astype(np.int64)
+            # tile position p -> image position (y0 + p // tw) * W + x0 + p % tw
+            p = loc - 1
+            want = np.where(loc > 0, (y0 + p // tw) * W + x0 + p % tw + 1, 0)
+            assert np.array_equal(got[y0:y0 + th, x0:x0 + tw], want), (y0, x0)
+
+
+def test_tile_independent_of_history(ccl):
+    # the same image twice, with a different image in between, gives the same bytes
+    a = wl.bernoulli(500, 700, 0.5, seed=1)
+    b = wl.blobs(900, 300, 4, seed=2)
+    first = gpu_label(ccl, a, 8)
+    gpu_label(ccl, b, 8)
+    assert np.array_equal(gpu_label(ccl, a, 8), first)
+
+
+# --- configs at full size ---------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(5))
+def test_c1_512_bernoulli(ccl, seed):
+    assert_parity(ccl, wl.bernoulli(512, 512, 0.5, seed=seed), 8, "C1")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("kind,kw", wl.single_image_contents())
+def test_c2_2048(ccl, kind, kw, conn):
+    img = cached(kind, 2048, 2048, 0, tuple(sorted(kw.items())))
+    assert_parity(ccl, img, conn, f"C2 {kind}{kw}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("kind,kw", wl.single_image_contents())
+def test_c2_4096(ccl, kind, kw, conn):
+    img = cached(kind, 4096, 4096, 0, tuple(sorted(kw.items())))
+    assert_parity(ccl, img, conn, f"C2 {kind}{kw}")
+
+
+@pytest.mark.parametrize("kind,kw", wl.ADVERSARIAL)
+def test_c3_8192_adversarial(ccl, kind, kw):
+    img = wl.make(kind, 8192, 8192, **kw)
+    assert_parity(ccl, img, 8, f"C3 {kind}{kw}")
+
+
+def test_batch_matches_single(ccl):
+    specs = wl.batch_specs(24, seed=3, lo=16, hi=700)
+    imgs = [wl.make(k, H, W, seed=s, **kw) for (H, W, k, kw, s) in specs]
+    conns = [8 if i % 3 else 4 for i in range(len(imgs))]
+    outs = ccl.label_batch([to_dev(im) for im in imgs], conns)
+    torch.cuda.synchronize()
+    for im, c, o in zip(imgs, conns, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle_label(im, c))
