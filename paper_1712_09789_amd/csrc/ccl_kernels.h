@@ -15,6 +15,7 @@ constexpr int TW = 64;
 #endif
 constexpr int TILE_ROWS = CCL_TILE_ROWS;
 constexpr int NSLOTS = 2 * TW + 2 * TILE_ROWS;  // border pixels per tile
+constexpr int RUNTAB_PER_TILE = TILE_ROWS * TW / 2;  // run-table entries per tile
 
 struct ImageArgs {
     const uint8_t* img;
@@ -32,12 +33,14 @@ struct Workspace {
     uint64_t* bits;    // [ntiles][TILE_ROWS] foreground masks
     int32_t* slots;    // [ntiles][NSLOTS] forest node of each border pixel, -1 = bg
     uint64_t* forest;  // [ntiles][NSLOTS] (key of parent << 32) | parent node
+    uint16_t* runtab;  // [ntiles][RUNTAB_PER_TILE] local root of each run
 };
 
 inline int64_t workspace_bytes(int64_t ntiles)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
-    return up(ntiles * TILE_ROWS * 8) + up(ntiles * NSLOTS * 4) + up(ntiles * NSLOTS * 8);
+    return up(ntiles * TILE_ROWS * 8) + up(ntiles * NSLOTS * 4) + up(ntiles * NSLOTS * 8) +
+           up(ntiles * RUNTAB_PER_TILE * 2);
 }
 
 inline Workspace carve_workspace(void* base, int64_t ntiles)
@@ -50,6 +53,8 @@ inline Workspace carve_workspace(void* base, int64_t ntiles)
     ws.slots = reinterpret_cast<int32_t*>(p);
     p += up(ntiles * NSLOTS * 4);
     ws.forest = reinterpret_cast<uint64_t*>(p);
+    p += up(ntiles * NSLOTS * 8);
+    ws.runtab = reinterpret_cast<uint16_t*>(p);
     return ws;
 }
 

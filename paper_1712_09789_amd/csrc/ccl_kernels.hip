@@ -1,27 +1,35 @@
 // Block-based coarse-to-fine connected-components labelling for gfx950.
 //
-// The image is cut into tiles of TW x TH pixels (TW = 64: one 64-bit mask
-// word per tile row).  One workgroup of TH threads owns a tile, one lane per
-// tile row, so the row-scan work of the paper's local step becomes bit
-// arithmetic on that lane's word.
+// The image is cut into tiles of 64 x TILE_ROWS pixels: one 64-bit
+// foreground mask per tile row, so the paper's row scan becomes bit
+// arithmetic on a word.  A workgroup of 256 threads owns a tile.
 //
-// Three kernels per image (Section 3 of the paper):
+// Nodes of the tile-local union-find are runs: maximal horizontal stretches
+// of foreground.  Under 8-connectivity two rows are fused into a strip first:
+// any run of (row 2k | row 2k+1) is 8-connected (neighbouring columns that
+// each hold a foreground pixel in one of the two rows always touch), so a
+// strip run is a node.  "Line" below means a row (4-connectivity) or a strip
+// (8-connectivity); runs get dense ids in line-major, left-to-right order.
+//
+// Three kernels per image (the paper's Section 3):
 //   k_local  (Section 3.1)  load the tile, label it in LDS, and publish what
-//            the merge needs: the foreground bitmask, one node id per border
-//            pixel, and one forest node per tile-local component that touches
-//            the tile border.
+//            the merge and the relabel need: the foreground bitmask, a run
+//            table (local root of each run), one forest node id per border
+//            pixel, and one forest node per component that touches the tile
+//            border.
 //   k_seam   (Section 3.2)  for every foreground pair straddling a tile seam,
 //            unite the two components' forest nodes in HBM (atomicMin).
-//   k_final  (Section 3.3)  relabel the tile from its bitmask (the local
-//            labelling is recomputed instead of stored), look up the global
-//            root of each border-touching component, and write every label
-//            exactly once.
+//   k_final  (Section 3.3)  look up the global root of each border component
+//            and write every label exactly once, from the bitmask and the run
+//            table (no union-find work is repeated).
 //
 // Labels are canonical: 1 + the smallest raster position of the component.
-// Inside a tile the root of a component is its smallest local position
-// (links always point the larger root at the smaller), which is also its
-// smallest raster position because both orders are row-major.  Across tiles
-// the forest orders roots by that raster position (the key).
+// Every node carries a key, the tile position of its smallest pixel; parents
+// are packed as (key << 16 | id), so "point the larger root at the smaller"
+// (the paper's merge) is an atomicMin on the packed word, and the root of a
+// tile component is the node with the smallest key.  Both tile order and
+// raster order are row-major, so the smallest key is the smallest raster
+// position.  Across tiles the HBM forest orders roots by raster position.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,25 +38,34 @@
 
 namespace ccl {
 
+constexpr int NT = 256;  // threads per tile workgroup
+
+// Geometry of one connectivity: D = 0 (4-connectivity, lines are rows) or
+// D = 1 (8-connectivity, lines are two-row strips).
+template <int D>
+struct Geo {
+    static constexpr int NL = D ? TILE_ROWS / 2 : TILE_ROWS;  // lines per tile
+    static constexpr int TPL = NT / NL;                       // threads per line
+    static constexpr int WIN = TW / TPL;                      // columns per thread
+    static constexpr int MAXR = NL * (TW / 2);                // runs per tile, at most
+};
+static_assert(Geo<0>::MAXR <= RUNTAB_PER_TILE && Geo<1>::MAXR <= RUNTAB_PER_TILE, "run table");
+static_assert(NSLOTS == NT, "one border slot per thread");
+
 // ---------------------------------------------------------------------------
 // bit helpers
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
 __device__ __forceinline__ int ctz64_or64(uint64_t v) { return v ? __builtin_ctzll(v) : 64; }
-__device__ __forceinline__ int msb64(uint64_t v) { return 63 - __builtin_clzll(v); }
+__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
 
-// Bits lo..hi (inclusive), 0 <= lo <= hi <= 63.
+// Bits 0..x inclusive (x in 0..63).
+__device__ __forceinline__ uint64_t upto(int x) { return (2ull << x) - 1ull; }
+// Bits lo..hi inclusive, 0 <= lo <= hi <= 63.
 __device__ __forceinline__ uint64_t span_mask(int lo, int hi)
 {
     return (~0ull << lo) & (~0ull >> (63 - hi));
-}
-
-// Start of the run that contains foreground bit x of a row, given the row's
-// run-start mask: the highest start bit at or below x.
-__device__ __forceinline__ int run_start(uint64_t starts, int x)
-{
-    return msb64(starts & ((2ull << x) - 1ull));
 }
 
 // Nonzero bytes of a dword -> 4-bit mask (bit i = byte i != 0).
@@ -59,8 +76,12 @@ __device__ __forceinline__ uint32_t nz_nibble(uint32_t d)
 }
 
 // ---------------------------------------------------------------------------
-// LDS union-find over tile positions (32-bit parents, parent <= self)
+// LDS union-find over run ids, parents packed as (key << 16) | id
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t pk(uint32_t key, uint32_t id) { return (key << 16) | id; }
+__device__ __forceinline__ uint32_t pk_id(uint32_t v) { return v & 0xffffu; }
+__device__ __forceinline__ uint32_t pk_key(uint32_t v) { return v >> 16; }
 
 __device__ __forceinline__ uint32_t lds_ld(const uint32_t* p)
 {
@@ -71,43 +92,44 @@ __device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Root of x, halving the path on the way (every write stores an ancestor,
-// which is smaller than the node, so no cycle can form).
-__device__ uint32_t lds_find(uint32_t* P, uint32_t x)
+// Packed root of x.  Halves the path on the way: every store writes the
+// grandparent, whose key is smaller, so entries only ever decrease.
+__device__ uint32_t pfind(uint32_t* P, uint32_t x)
 {
-    while (true) {
-        uint32_t p = lds_ld(P + x);
-        if (p == x) return x;
-        uint32_t gp = lds_ld(P + p);
-        if (gp == p) return p;
-        lds_st(P + x, gp);
-        x = gp;
+    uint32_t v = lds_ld(P + x);
+    while (pk_id(v) != x) {
+        const uint32_t p = pk_id(v);
+        const uint32_t w = lds_ld(P + p);
+        if (pk_id(w) == p) return w;
+        lds_st(P + x, w);
+        x = pk_id(w);
+        v = lds_ld(P + x);
     }
+    return v;
 }
 
-// The paper's merge (Section 3.1.3): compare the two roots and point the
-// larger at the smaller, atomically; if the larger stopped being a root in
-// the meantime, continue with the parent it had.
-__device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b)
+// The paper's merge (Section 3.1.3): compare the two roots and point the one
+// with the larger key at the other, atomically; if it stopped being a root
+// in the meantime, continue with the parent it had.
+__device__ void punion(uint32_t* P, uint32_t a, uint32_t b)
 {
     while (true) {
-        a = lds_find(P, a);
-        b = lds_find(P, b);
-        if (a == b) return;
-        if (a < b) { uint32_t t = a; a = b; b = t; }
-        uint32_t old = __hip_atomic_fetch_min(P + a, b, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (old == a) return;
-        a = old;
+        uint32_t ra = pfind(P, a), rb = pfind(P, b);
+        if (ra == rb) return;
+        if (ra < rb) { uint32_t t = ra; ra = rb; rb = t; }
+        const uint32_t old = __hip_atomic_fetch_min(P + pk_id(ra), rb, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == ra) return;
+        a = pk_id(old);
+        b = pk_id(rb);
     }
 }
 
 // ---------------------------------------------------------------------------
 // HBM forest over border components.  Entry = (key of parent << 32) | parent
-// node; a root stores its own key and id.  Keys (raster position of a tile's
-// local root) are distinct across components, so ordering by the packed
-// value orders by key: atomicMin on it only ever moves a parent to a smaller
-// key, the global analogue of "larger root points at the smaller".
+// node; a root stores its own key and id.  Keys (raster position of a tile
+// component's smallest pixel) are distinct across components, so atomicMin
+// on the packed word only ever moves a parent to a smaller key.
 // ---------------------------------------------------------------------------
 
 struct Root {
@@ -152,10 +174,10 @@ __device__ void g_union(uint64_t* F, uint32_t a, uint32_t b)
         if (ra.node == rb.node) return;
         if (ra.key < rb.key) { Root t = ra; ra = rb; rb = t; }
         // ra has the larger key: link it under rb
-        uint64_t self = ((uint64_t)ra.key << 32) | ra.node;
-        uint64_t nv = ((uint64_t)rb.key << 32) | rb.node;
-        uint64_t old = __hip_atomic_fetch_min(F + ra.node, nv, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t self = ((uint64_t)ra.key << 32) | ra.node;
+        const uint64_t nv = ((uint64_t)rb.key << 32) | rb.node;
+        const uint64_t old = __hip_atomic_fetch_min(F + ra.node, nv, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
         if (old == self) return;
         a = (uint32_t)old;
         b = rb.node;
@@ -163,180 +185,286 @@ __device__ void g_union(uint64_t* F, uint32_t a, uint32_t b)
 }
 
 // ---------------------------------------------------------------------------
-// tile-local labelling (shared by k_local and k_final)
+// line structure shared by k_local and k_final
 // ---------------------------------------------------------------------------
 
-template <int TH>
-struct TileShared {
-    uint32_t P[TW * TH];  // parent of each run start (position y*TW + x)
-    uint64_t M[TH];       // foreground mask per tile row
-    uint64_t S[TH];       // run-start mask per tile row
-    int32_t slot_lr[2 * TW + 2 * TH];  // local root of each border slot, -1 = bg
+template <int D>
+struct Lines {
+    uint64_t M[TILE_ROWS];          // foreground mask of each tile row
+    uint64_t LM[Geo<D>::NL];        // foreground columns of each line
+    uint64_t LS[Geo<D>::NL];        // run starts of each line
+    uint32_t base[Geo<D>::NL + 1];  // id of the first run of each line; base[NL] = runs
+};
+
+// Row masks in sh.M -> line masks, run starts and dense run-id bases.  Must be
+// called by all threads; ends with a barrier.
+template <int D>
+__device__ void build_lines(Lines<D>& sh, int tid)
+{
+    constexpr int NL = Geo<D>::NL;
+    if (tid < 64) {
+        uint32_t cnt = 0;
+        if (tid < NL) {
+            const uint64_t lm = D ? (sh.M[2 * tid] | sh.M[2 * tid + 1]) : sh.M[tid];
+            const uint64_t ls = lm & ~(lm << 1);
+            sh.LM[tid] = lm;
+            sh.LS[tid] = ls;
+            cnt = popc64(ls);
+        }
+        // inclusive scan of the run counts across the first wavefront
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if (tid >= off) inc += o;
+        }
+        if (tid < NL) sh.base[tid] = inc - cnt;
+        if (tid == NL - 1) sh.base[NL] = inc;
+    }
+    __syncthreads();
+}
+
+// Dense id of the run of line l that contains foreground column x.
+template <int D>
+__device__ __forceinline__ uint32_t run_id(const Lines<D>& sh, int l, int x)
+{
+    return sh.base[l] + popc64(sh.LS[l] & upto(x)) - 1u;
+}
+
+// Row of line l that faces the line above / below it.
+template <int D>
+__device__ __forceinline__ uint64_t top_row(const Lines<D>& sh, int l)
+{
+    return D ? sh.M[2 * l] : sh.M[l];
+}
+template <int D>
+__device__ __forceinline__ uint64_t bottom_row(const Lines<D>& sh, int l)
+{
+    return D ? sh.M[2 * l + 1] : sh.M[l];
+}
+
+// Tile position (y * 64 + x) of the smallest pixel of run [a, e] of line l.
+template <int D>
+__device__ __forceinline__ uint32_t run_key(const Lines<D>& sh, int l, int a, int e)
+{
+    if (!D) return (uint32_t)(l * TW + a);
+    const uint64_t top = sh.M[2 * l] & span_mask(a, e);
+    return top ? (uint32_t)(2 * l * TW + ctz64(top)) : (uint32_t)((2 * l + 1) * TW + a);
+}
+
+template <int D>
+struct LocalShared : Lines<D> {
+    uint32_t P[Geo<D>::MAXR];
     union {
-        uint16_t h[TH * 4];  // 16-pixel masks as produced by the byte load
-        uint64_t w[TH];      // the same bits as one word per row
+        uint16_t h[TILE_ROWS * 4];  // 16-pixel masks as produced by the byte load
+        uint64_t w[TILE_ROWS];      // the same bits as one word per row
     } m16;
 };
 
-// Column connection, unification, refinement and the final flatten of the
-// local step (Section 3.1.2-3.1.3), at run granularity.  On entry M and S
-// hold the tile's masks; on exit P[y*TW + a] is the local root for every run
-// start a of every row y.  D is the neighbourhood reach across rows:
-// 0 for 4-connectivity, 1 for 8-connectivity (diagonals).
-template <int TH, int D>
-__device__ void label_tile(TileShared<TH>& sh, int y)
-{
-    const uint64_t m = sh.M[y];
-    const uint64_t s = sh.S[y];
-    const uint64_t mu = y > 0 ? sh.M[y - 1] : 0ull;
-    const uint64_t su = y > 0 ? sh.S[y - 1] : 0ull;
-    const uint32_t row = (uint32_t)y * TW;
-
-    // Coarse column connection: each run records the lowest label among its
-    // neighbours in the row above, i.e. the run holding the leftmost
-    // neighbouring pixel there; a run with no such neighbour is a root.
-    for (uint64_t r = s; r; r &= r - 1) {
-        int a = ctz64(r);
-        int b = a + ctz64_or64(~(m >> a)) - 1;
-        uint64_t u = mu & span_mask(a > D ? a - D : 0, b + D < 63 ? b + D : 63);
-        uint32_t p = row + a;
-        if (u) p = row - TW + run_start(su, ctz64(u));
-        sh.P[row + a] = p;
-    }
-    __syncthreads();
-
-    // Label-equivalence unification: flatten every run to its current root.
-    for (uint64_t r = s; r; r &= r - 1) {
-        uint32_t i = row + ctz64(r);
-        lds_st(sh.P + i, lds_find(sh.P, i));
-    }
-    __syncthreads();
-
-    // Refinement: every run of the row above is united with the run holding
-    // the leftmost neighbouring pixel in this row.  Together with the coarse
-    // links (leftmost neighbour above each run) this covers every adjacency
-    // between the two rows: if runs A (this row) and B (above) touch but
-    // neither is the other's leftmost neighbour, then A's leftmost neighbour
-    // B' and B's leftmost neighbour A' lie further left and touch each other,
-    // so A - B' - A' - B is already connected by induction.
-    for (uint64_t r = su; r; r &= r - 1) {
-        int c = ctz64(r);
-        int e = c + ctz64_or64(~(mu >> c)) - 1;
-        uint64_t u = m & span_mask(c > D ? c - D : 0, e + D < 63 ? e + D : 63);
-        if (u) lds_union(sh.P, row - TW + c, row + run_start(s, ctz64(u)));
-    }
-    __syncthreads();
-
-    for (uint64_t r = s; r; r &= r - 1) {
-        uint32_t i = row + ctz64(r);
-        lds_st(sh.P + i, lds_find(sh.P, i));
-    }
-    __syncthreads();
-}
-
 // Border slot s -> tile-local (x, y).  Slots: top row, bottom row, left
 // column, right column.
-template <int TH>
 __device__ __forceinline__ void slot_xy(int s, int& x, int& y)
 {
     if (s < TW) { x = s; y = 0; }
-    else if (s < 2 * TW) { x = s - TW; y = TH - 1; }
-    else if (s < 2 * TW + TH) { x = 0; y = s - 2 * TW; }
-    else { x = TW - 1; y = s - 2 * TW - TH; }
+    else if (s < 2 * TW) { x = s - TW; y = TILE_ROWS - 1; }
+    else if (s < 2 * TW + TILE_ROWS) { x = 0; y = s - 2 * TW; }
+    else { x = TW - 1; y = s - 2 * TW - TILE_ROWS; }
 }
 
-// Local root of every border slot into sh.slot_lr (-1 for background).
-template <int TH>
-__device__ void border_roots(TileShared<TH>& sh, int lane)
-{
-    constexpr int NS = 2 * TW + 2 * TH;
-    for (int s = lane; s < NS; s += TH) {
-        int x, y;
-        slot_xy<TH>(s, x, y);
-        int32_t lr = -1;
-        if ((sh.M[y] >> x) & 1ull)
-            lr = (int32_t)lds_ld(sh.P + y * TW + run_start(sh.S[y], x));
-        sh.slot_lr[s] = lr;
-    }
-}
+// Run-table entry flags: the run's component touches the tile border (low
+// bits = representative border slot) / this run is that component's root.
+constexpr uint16_t RT_BORDER = 0x8000;
+constexpr uint16_t RT_ROOT = 0x4000;
+constexpr uint32_t REP_TAG = 0x80000000u;
 
 // ---------------------------------------------------------------------------
 // k_local
 // ---------------------------------------------------------------------------
 
-template <int TH, int D>
-__global__ __launch_bounds__(TH) void k_local(ImageArgs a, Workspace ws)
+template <int D>
+__global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
 {
-    constexpr int NS = 2 * TW + 2 * TH;
-    __shared__ TileShared<TH> sh;
-    const int lane = threadIdx.x;
+    using G = Geo<D>;
+    __shared__ LocalShared<D> sh;
+    const int tid = threadIdx.x;
     const int t = blockIdx.x;
     const int tx = t % a.ntx, ty = t / a.ntx;
-    const int gx0 = tx * TW, gy0 = ty * TH;
+    const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
-    // Initialisation: load the tile's bytes, four lanes per row, sixteen
-    // pixels per lane, and turn them into foreground bits.
-    for (int c = lane; c < TH * 4; c += TH) {
-        int r = c >> 2, q = c & 3;
-        int gy = gy0 + r, gx = gx0 + 16 * q;
+    // Initialisation: load the tile's bytes, four threads per row, sixteen
+    // pixels per thread, and turn them into foreground bits.
+    for (int c = tid; c < TILE_ROWS * 4; c += NT) {
+        const int r = c >> 2, q = c & 3;
+        const int gy = gy0 + r, gx = gx0 + 16 * q;
         uint32_t bits = 0;
         if (gy < a.H && gx < a.W) {
             const uint8_t* src = a.img + (int64_t)gy * a.pitch + gx;
             if (a.vec_in && gx + 16 <= a.W) {
-                uint4 v = *reinterpret_cast<const uint4*>(src);
-                bits = nz_nibble(v.x) | (nz_nibble(v.y) << 4) |
-                       (nz_nibble(v.z) << 8) | (nz_nibble(v.w) << 12);
+                const uint4 v = *reinterpret_cast<const uint4*>(src);
+                bits = nz_nibble(v.x) | (nz_nibble(v.y) << 4) | (nz_nibble(v.z) << 8) |
+                       (nz_nibble(v.w) << 12);
             } else {
-                int n = a.W - gx < 16 ? a.W - gx : 16;
+                const int n = a.W - gx < 16 ? a.W - gx : 16;
                 for (int i = 0; i < n; ++i) bits |= (uint32_t)(src[i] != 0) << i;
             }
         }
         sh.m16.h[c] = (uint16_t)bits;
     }
     __syncthreads();
+    if (tid < TILE_ROWS) {
+        const uint64_t m = sh.m16.w[tid];
+        sh.M[tid] = m;
+        ws.bits[(int64_t)t * TILE_ROWS + tid] = m;
+    }
+    __syncthreads();
+    build_lines<D>(sh, tid);
+
+    // This thread's line and column window; its runs are those starting in
+    // the window, with consecutive ids from id0.
+    const int l = tid / G::TPL;
+    const int wlo = (tid % G::TPL) * G::WIN;
+    const uint64_t wmask = (G::WIN == 64 ? ~0ull : ((1ull << G::WIN) - 1ull)) << wlo;
+    const uint64_t lm = sh.LM[l];
+    const uint64_t mine = sh.LS[l] & wmask;
+    const uint32_t id0 = sh.base[l] + popc64(sh.LS[l] & ~(~0ull << wlo));
+
+    // Row connection: a run is its own provisional root, keyed by its
+    // smallest pixel (the paper's provisional label = position).
     {
-        const uint64_t m = sh.m16.w[lane];
-        sh.M[lane] = m;
-        sh.S[lane] = m & ~(m << 1);
-        ws.bits[(int64_t)t * TH + lane] = m;
+        uint32_t id = id0;
+        for (uint64_t r = mine; r; r &= r - 1, ++id) {
+            const int s0 = ctz64(r);
+            const int e = s0 + ctz64_or64(~(lm >> s0)) - 1;
+            sh.P[id] = pk(run_key<D>(sh, l, s0, e), id);
+        }
     }
     __syncthreads();
 
-    label_tile<TH, D>(sh, lane);
-
-    border_roots<TH>(sh, lane);
-    __syncthreads();
-
-    // Elect one representative border slot per component (the smallest slot
-    // index) by an atomic max on the root's entry; root entries are no
-    // longer needed as parents.
-    constexpr uint32_t REP = 0x40000000u;
-    for (int s = lane; s < NS; s += TH) {
-        int32_t lr = sh.slot_lr[s];
-        if (lr >= 0)
-            __hip_atomic_fetch_max(sh.P + lr, REP | (uint32_t)(NS - 1 - s),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // Column connection (coarse): each run records the lowest label among
+    // its neighbours in the line above, i.e. the run holding the leftmost
+    // pixel there that touches it.  One plain store per run.
+    if (l > 0) {
+        const uint64_t up = bottom_row<D>(sh, l - 1);
+        const uint64_t top = top_row<D>(sh, l);
+        uint32_t id = id0;
+        for (uint64_t r = mine; r; r &= r - 1, ++id) {
+            const int s0 = ctz64(r);
+            const int e = s0 + ctz64_or64(~(lm >> s0)) - 1;
+            const uint64_t mt = top & span_mask(s0, e);
+            const uint64_t reach = D ? (mt | (mt << 1) | (mt >> 1)) : mt;
+            const uint64_t contact = up & reach;
+            if (contact) sh.P[id] = lds_ld(sh.P + run_id<D>(sh, l - 1, ctz64(contact)));
+        }
     }
     __syncthreads();
 
-    // ID conversion (Section 3.1.4) for border components: the node of the
-    // representative slot carries the raster position of the local root.
-    const int64_t base = (int64_t)t * NS;
-    for (int s = lane; s < NS; s += TH) {
-        int32_t lr = sh.slot_lr[s];
-        int32_t node = -1;
-        if (lr >= 0) {
-            int rep = NS - 1 - (int)(lds_ld(sh.P + lr) & ~REP);
-            node = (int32_t)(base + rep);
-            if (rep == s) {
-                uint32_t key = (uint32_t)((gy0 + lr / TW) * (int64_t)a.W + gx0 + lr % TW);
-                ws.forest[node] = ((uint64_t)key << 32) | (uint32_t)node;
+    // Label-equivalence unification: every run points at its current root.
+    {
+        uint32_t id = id0;
+        for (uint64_t r = mine; r; r &= r - 1, ++id) lds_st(sh.P + id, pfind(sh.P, id));
+    }
+    __syncthreads();
+
+    // Refinement: unite the runs of every remaining adjacency between this
+    // line and the one above.  The adjacencies are enumerated bitwise from
+    // the two facing rows (lower = this line's top row T, upper = the line
+    // above's bottom row B); an edge is dropped when an edge further left
+    // joins the same two runs (consecutive foreground pixels of one row lie
+    // in one run), which leaves one edge per touching pair of runs:
+    //   4-connectivity: starts of the stretches of T & B;
+    //   8-connectivity: (i,i)   where neither side continues from i-1,
+    //                   (i-1,i) where B does not continue from i-1,
+    //                   (i,i-1) where T does not continue from i-1.
+    if (l > 0) {
+        const uint64_t T = top_row<D>(sh, l), B = bottom_row<D>(sh, l - 1);
+        if (!D) {
+            const uint64_t o = T & B;
+            for (uint64_t r = o & ~(o << 1) & wmask; r; r &= r - 1) {
+                const int i = ctz64(r);
+                punion(sh.P, run_id<D>(sh, l, i), run_id<D>(sh, l - 1, i));
+            }
+        } else {
+            const uint64_t e0 = T & B & ~(T << 1) & ~(B << 1);
+            const uint64_t e1 = (T << 1) & B & ~(B << 1);
+            const uint64_t e2 = T & (B << 1) & ~(T << 1);
+            for (uint64_t r = e0 & wmask; r; r &= r - 1) {
+                const int i = ctz64(r);
+                punion(sh.P, run_id<D>(sh, l, i), run_id<D>(sh, l - 1, i));
+            }
+            for (uint64_t r = e1 & wmask; r; r &= r - 1) {
+                const int i = ctz64(r);
+                punion(sh.P, run_id<D>(sh, l, i - 1), run_id<D>(sh, l - 1, i));
+            }
+            for (uint64_t r = e2 & wmask; r; r &= r - 1) {
+                const int i = ctz64(r);
+                punion(sh.P, run_id<D>(sh, l, i), run_id<D>(sh, l - 1, i - 1));
             }
         }
-        ws.slots[base + s] = node;
+    }
+    __syncthreads();
+
+    // Unification again: every run points straight at its final local root.
+    {
+        uint32_t id = id0;
+        for (uint64_t r = mine; r; r &= r - 1, ++id) lds_st(sh.P + id, pfind(sh.P, id));
+    }
+    __syncthreads();
+
+    // Border slots (one per thread): local root of each border pixel.
+    const int s = tid;
+    int sx, sy;
+    slot_xy(s, sx, sy);
+    const bool fg = (sh.M[sy] >> sx) & 1ull;
+    uint32_t root = 0, rkey = 0;
+    if (fg) {
+        const uint32_t v = lds_ld(sh.P + run_id<D>(sh, D ? sy >> 1 : sy, sx));
+        root = pk_id(v);
+        rkey = pk_key(v);
+    }
+    __syncthreads();
+    // Elect the smallest slot of each border component as its representative
+    // (an atomic max on the root entry, which is no longer needed as a parent).
+    if (fg)
+        __hip_atomic_fetch_max(sh.P + root, REP_TAG | (uint32_t)(NSLOTS - 1 - s),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+
+    // ID conversion (Section 3.1.4): the representative's forest node carries
+    // the raster position of the component's smallest pixel.
+    const int64_t sbase = (int64_t)t * NSLOTS;
+    {
+        int32_t node = -1;
+        if (fg) {
+            const int rep = NSLOTS - 1 - (int)pk_id(lds_ld(sh.P + root));
+            node = (int32_t)(sbase + rep);
+            if (rep == s) {
+                const uint32_t gkey = (uint32_t)((int64_t)(gy0 + (int)(rkey / TW)) * a.W +
+                                                 gx0 + (int)(rkey % TW));
+                ws.forest[node] = ((uint64_t)gkey << 32) | (uint32_t)node;
+            }
+        }
+        ws.slots[sbase + s] = node;
+    }
+
+    // Run table: interior components store their root's tile key; border
+    // components store their representative slot (and mark the root run).
+    {
+        uint16_t* rt = ws.runtab + (int64_t)t * RUNTAB_PER_TILE;
+        uint32_t id = id0;
+        for (uint64_t r = mine; r; r &= r - 1, ++id) {
+            const uint32_t v = lds_ld(sh.P + id);
+            uint16_t ent;
+            if (v & REP_TAG) {
+                ent = (uint16_t)(RT_BORDER | RT_ROOT | (NSLOTS - 1 - pk_id(v)));
+            } else {
+                const uint32_t w = pk_id(v) == id ? v : lds_ld(sh.P + pk_id(v));
+                ent = (w & REP_TAG) ? (uint16_t)(RT_BORDER | (NSLOTS - 1 - pk_id(w)))
+                                    : (uint16_t)pk_key(v);
+            }
+            rt[id] = ent;
+        }
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // k_seam
@@ -374,10 +502,10 @@ __device__ __forceinline__ void seam_item(uint64_t* F, int32_t a_prev, int32_t a
 // Horizontal seams (between tile rows) run over the full image width, so
 // diagonal pairs through a four-tile corner are seen there; vertical seams
 // (between tile columns) stay inside one tile row.
-template <int TH, int D>
+template <int D>
 __global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
 {
-    constexpr int NS = 2 * TW + 2 * TH;
+    constexpr int NS = NSLOTS;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nh = (int64_t)(a.nty - 1) * a.W;
     const int64_t nv = (int64_t)(a.ntx - 1) * a.H;
@@ -399,8 +527,8 @@ __global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
         const int64_t g = gid - nh;
         const int j = (int)(g / a.H) + 1;
         const int y = (int)(g - (int64_t)(j - 1) * a.H);
-        const int k = y / TH, yl = y - k * TH;
-        const int64_t left = ((int64_t)k * a.ntx + j - 1) * NS + 2 * TW + TH;
+        const int k = y / TILE_ROWS, yl = y - k * TILE_ROWS;
+        const int64_t left = ((int64_t)k * a.ntx + j - 1) * NS + 2 * TW + TILE_ROWS;
         const int64_t right = ((int64_t)k * a.ntx + j) * NS + 2 * TW;
         a_cur = slots[left + yl];
         b_cur = slots[right + yl];
@@ -418,80 +546,73 @@ __global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
 // k_final
 // ---------------------------------------------------------------------------
 
-// Update of the global label map (Section 3.3).  The tile's local labelling
-// is rebuilt from the bitmask k_local stored; each border component takes the
-// key of its global root, every other component keeps its own local root; a
-// label is written once per pixel.  With LOCAL_ONLY the global lookup is
-// skipped (every tile labelled as a separate image).
-template <int TH, int D, bool LOCAL_ONLY>
-__global__ __launch_bounds__(TH) void k_final(ImageArgs a, Workspace ws)
+template <int D>
+struct FinalShared : Lines<D> {
+    int32_t lab[Geo<D>::MAXR];  // final label of each run
+    int32_t fin[NSLOTS];        // final label of each border component, by slot
+};
+
+// Update of the global label map (Section 3.3).  Each border component takes
+// 1 + the key of its global root, every other component 1 + the raster
+// position of its local root; each label is written once.  With LOCAL_ONLY
+// the forest is read before any merge (every tile labelled as an image).
+template <int D, bool LOCAL_ONLY>
+__global__ __launch_bounds__(NT) void k_final(ImageArgs a, Workspace ws)
 {
-    constexpr int NS = 2 * TW + 2 * TH;
-    constexpr uint32_t FIN = 0x80000000u;  // entry holds a final label
-    __shared__ TileShared<TH> sh;
-    const int lane = threadIdx.x;
+    __shared__ FinalShared<D> sh;
+    const int tid = threadIdx.x;
     const int t = blockIdx.x;
     const int tx = t % a.ntx, ty = t / a.ntx;
-    const int gx0 = tx * TW, gy0 = ty * TH;
+    const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
-    {
-        const uint64_t m = ws.bits[(int64_t)t * TH + lane];
-        sh.M[lane] = m;
-        sh.S[lane] = m & ~(m << 1);
-    }
+    if (tid < TILE_ROWS) sh.M[tid] = ws.bits[(int64_t)t * TILE_ROWS + tid];
     __syncthreads();
+    build_lines<D>(sh, tid);
+    const uint32_t R = sh.base[Geo<D>::NL];
+    const uint16_t* rt = ws.runtab + (int64_t)t * RUNTAB_PER_TILE;
+    const int64_t sbase = (int64_t)t * NSLOTS;
 
-    label_tile<TH, D>(sh, lane);
-
-    if (!LOCAL_ONLY) {
-        border_roots<TH>(sh, lane);
-        __syncthreads();
-        // the representative slot of each border component looks up its root
-        const int64_t base = (int64_t)t * NS;
-        for (int s = lane; s < NS; s += TH) {
-            int32_t lr = sh.slot_lr[s];
-            if (lr >= 0 && ws.slots[base + s] == (int32_t)(base + s)) {
-                Root r = g_find_ro(ws.forest, (uint32_t)(base + s));
-                lds_st(sh.P + lr, FIN | (r.key + 1u));
-            }
+    // global root of each border component, looked up once (by its root run)
+    for (uint32_t id = tid; id < R; id += NT) {
+        const uint16_t e = rt[id];
+        if ((e & (RT_BORDER | RT_ROOT)) == (RT_BORDER | RT_ROOT)) {
+            const int rep = e & 0x3fff;
+            const uint32_t key = LOCAL_ONLY
+                                     ? (uint32_t)(g_ld(ws.forest + sbase + rep) >> 32)
+                                     : g_find_ro(ws.forest, (uint32_t)(sbase + rep)).key;
+            sh.fin[rep] = (int32_t)(key + 1u);
         }
-        __syncthreads();
-    }
-
-    // roots of components that stay inside the tile: ID conversion of the
-    // local root (Section 3.1.4)
-    const uint64_t m = sh.M[lane], s = sh.S[lane];
-    const uint32_t row = (uint32_t)lane * TW;
-    for (uint64_t r = s; r; r &= r - 1) {
-        const uint32_t i = row + ctz64(r);
-        if (lds_ld(sh.P + i) == i)
-            lds_st(sh.P + i, FIN | (uint32_t)((gy0 + lane) * (int64_t)a.W + gx0 + (int)(i - row) + 1));
     }
     __syncthreads();
-    // every other run start copies its root's final label
-    for (uint64_t r = s; r; r &= r - 1) {
-        const uint32_t i = row + ctz64(r);
-        const uint32_t v = lds_ld(sh.P + i);
-        if (!(v & FIN)) lds_st(sh.P + i, lds_ld(sh.P + v));
+    for (uint32_t id = tid; id < R; id += NT) {
+        const uint16_t e = rt[id];
+        int32_t v;
+        if (e & RT_BORDER) {
+            v = sh.fin[e & 0x3fff];
+        } else {
+            // ID conversion of an interior component's local root
+            v = (int32_t)((int64_t)(gy0 + e / TW) * a.W + gx0 + e % TW + 1);
+        }
+        sh.lab[id] = v;
     }
     __syncthreads();
-    (void)m;
 
-    // write the labels: 16 lanes per tile row, 4 pixels per lane
+    // write the labels: 16 threads per tile row, 4 pixels per thread
     const int xmax = a.W - gx0;  // pixels of this tile inside the image
-    for (int c = lane; c < TH * 16; c += TH) {
-        const int r = c >> 4, q = c & 15;
+    for (int c = tid; c < TILE_ROWS * 16; c += NT) {
+        const int r = c >> 4, x0 = (c & 15) * 4;
         const int gy = gy0 + r;
-        const int x0 = q * 4;
         if (gy >= a.H || x0 >= xmax) continue;
-        const uint64_t mr = sh.M[r], sr = sh.S[r];
+        const int l = D ? r >> 1 : r;
+        const uint64_t mr = sh.M[r], ls = sh.LS[l];
+        uint32_t cnt = sh.base[l] + popc64(ls & ~(~0ull << x0));  // runs starting left of x0
         int32_t v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int x = x0 + k;
-            v[k] = ((mr >> x) & 1ull)
-                       ? (int32_t)(lds_ld(sh.P + r * TW + run_start(sr, x)) & ~FIN)
-                       : 0;
+            cnt += (uint32_t)((ls >> x) & 1ull);
+            // a foreground pixel has its run start at or left of it, so cnt >= 1
+            v[k] = ((mr >> x) & 1ull) ? sh.lab[cnt ? cnt - 1 : 0] : 0;
         }
         int32_t* dst = a.labels + (int64_t)gy * a.W + gx0 + x0;
         if (a.vec_out && x0 + 4 <= xmax) {
@@ -519,28 +640,28 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
 // launchers
 // ---------------------------------------------------------------------------
 
-template <int TH, int D>
+template <int D>
 static hipError_t launch_all(const ImageArgs& a, const Workspace& ws, hipStream_t st,
                              KernelTimer* timer, bool local_only)
 {
     const unsigned ntiles = (unsigned)a.ntx * (unsigned)a.nty;
     timer_begin(timer, KIND_LOCAL, st);
-    k_local<TH, D><<<ntiles, TH, 0, st>>>(a, ws);
+    k_local<D><<<ntiles, NT, 0, st>>>(a, ws);
     timer_end(timer, KIND_LOCAL, st);
     if (local_only) {
         timer_begin(timer, KIND_FINAL, st);
-        k_final<TH, D, true><<<ntiles, TH, 0, st>>>(a, ws);
+        k_final<D, true><<<ntiles, NT, 0, st>>>(a, ws);
         timer_end(timer, KIND_FINAL, st);
         return hipGetLastError();
     }
     const int64_t items = (int64_t)(a.nty - 1) * a.W + (int64_t)(a.ntx - 1) * a.H;
     if (items > 0) {
         timer_begin(timer, KIND_SEAM, st);
-        k_seam<TH, D><<<(unsigned)((items + 255) / 256), 256, 0, st>>>(a, ws);
+        k_seam<D><<<(unsigned)((items + 255) / 256), 256, 0, st>>>(a, ws);
         timer_end(timer, KIND_SEAM, st);
     }
     timer_begin(timer, KIND_FINAL, st);
-    k_final<TH, D, false><<<ntiles, TH, 0, st>>>(a, ws);
+    k_final<D, false><<<ntiles, NT, 0, st>>>(a, ws);
     timer_end(timer, KIND_FINAL, st);
     return hipGetLastError();
 }
@@ -548,8 +669,8 @@ static hipError_t launch_all(const ImageArgs& a, const Workspace& ws, hipStream_
 hipError_t launch_label(const ImageArgs& a, const Workspace& ws, hipStream_t st,
                         KernelTimer* timer, bool local_only)
 {
-    if (a.conn == 8) return launch_all<TILE_ROWS, 1>(a, ws, st, timer, local_only);
-    return launch_all<TILE_ROWS, 0>(a, ws, st, timer, local_only);
+    if (a.conn == 8) return launch_all<1>(a, ws, st, timer, local_only);
+    return launch_all<0>(a, ws, st, timer, local_only);
 }
 
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,
