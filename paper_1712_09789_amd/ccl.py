@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libccl.so")
 CCL_OK = 0
 STATUS_NAMES = {0: "CCL_OK", -1: "CCL_ERR_INVALID_ARG", -2: "CCL_ERR_TOO_LARGE",
                 -3: "CCL_ERR_OUT_OF_MEMORY", -4: "CCL_ERR_HIP"}
-KERNEL_KINDS = ("local", "seam", "final", "copy")
+KERNEL_KINDS = ("local", "seam", "final", "copy", "block")
 
 
 class CCLError(RuntimeError):
@@ -166,12 +166,13 @@ def timing_enable(on: bool = True) -> None:
 
 
 def timing_read() -> dict:
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_int64 * 4)()
-    k = _lib.ccl_timing_read(ms, n, 4)
+    nk = len(KERNEL_KINDS)
+    ms = (ctypes.c_double * nk)()
+    n = (ctypes.c_int64 * nk)()
+    k = _lib.ccl_timing_read(ms, n, nk)
     if k < 0:
         _check(k)
-    return {KERNEL_KINDS[i]: (float(ms[i]), int(n[i])) for i in range(4)}
+    return {KERNEL_KINDS[i]: (float(ms[i]), int(n[i])) for i in range(nk)}
 
 
 def copy_bytes(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

@@ -26,6 +26,7 @@ struct ImageArgs {
     int32_t conn;      // 4 or 8
     int32_t vec_in;    // img and pitch are 16-byte aligned
     int32_t vec_out;   // labels rows are 16-byte aligned (W % 4 == 0)
+    uint32_t wmagic;   // floor(2^32 / W) (0xffffffff for W = 1), for division by W
 };
 
 // Device workspace of one image.
@@ -58,7 +59,7 @@ inline Workspace carve_workspace(void* base, int64_t ntiles)
     return ws;
 }
 
-enum { KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, NKINDS = 4 };
+enum { KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, KIND_BLOCK = 4, NKINDS = 5 };
 
 struct KernelTimer;  // host-side event recorder, null when timing is off
 void timer_begin(KernelTimer* t, int kind, hipStream_t st);

@@ -59,6 +59,7 @@ static_assert(NSLOTS == NT, "one border slot per thread");
 __device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
 __device__ __forceinline__ int ctz64_or64(uint64_t v) { return v ? __builtin_ctzll(v) : 64; }
 __device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
+__device__ __forceinline__ int msb64(uint64_t v) { return 63 - __builtin_clzll(v); }
 
 // Bits 0..x inclusive (x in 0..63).
 __device__ __forceinline__ uint64_t upto(int x) { return (2ull << x) - 1ull; }
@@ -328,24 +329,18 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
     const uint64_t mine = sh.LS[l] & wmask;
     const uint32_t id0 = sh.base[l] + popc64(sh.LS[l] & ~(~0ull << wlo));
 
-    // Row connection: a run is its own provisional root, keyed by its
-    // smallest pixel (the paper's provisional label = position).
+    // Row connection and column connection (coarse), one pass over the runs.
+    // A run is a provisional label keyed by its smallest pixel (the paper's
+    // provisional label = position); a run that touches the line above
+    // records the lowest label among its neighbours there instead, i.e. the
+    // run holding the leftmost pixel of that line's facing row that touches
+    // it.  One plain store per run: every entry is written by its owner only.
     {
-        uint32_t id = id0;
-        for (uint64_t r = mine; r; r &= r - 1, ++id) {
-            const int s0 = ctz64(r);
-            const int e = s0 + ctz64_or64(~(lm >> s0)) - 1;
-            sh.P[id] = pk(run_key<D>(sh, l, s0, e), id);
-        }
-    }
-    __syncthreads();
-
-    // Column connection (coarse): each run records the lowest label among
-    // its neighbours in the line above, i.e. the run holding the leftmost
-    // pixel there that touches it.  One plain store per run.
-    if (l > 0) {
-        const uint64_t up = bottom_row<D>(sh, l - 1);
         const uint64_t top = top_row<D>(sh, l);
+        const uint64_t up = l > 0 ? bottom_row<D>(sh, l - 1) : 0ull;
+        const uint64_t lsu = l > 0 ? sh.LS[l - 1] : 0ull;
+        const uint64_t lmu = l > 0 ? sh.LM[l - 1] : 0ull;
+        const uint32_t baseu = l > 0 ? sh.base[l - 1] : 0u;
         uint32_t id = id0;
         for (uint64_t r = mine; r; r &= r - 1, ++id) {
             const int s0 = ctz64(r);
@@ -353,7 +348,16 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
             const uint64_t mt = top & span_mask(s0, e);
             const uint64_t reach = D ? (mt | (mt << 1) | (mt >> 1)) : mt;
             const uint64_t contact = up & reach;
-            if (contact) sh.P[id] = lds_ld(sh.P + run_id<D>(sh, l - 1, ctz64(contact)));
+            uint32_t v;
+            if (contact) {
+                const uint64_t below = lsu & upto(ctz64(contact));
+                const int c = msb64(below);
+                const int ce = c + ctz64_or64(~(lmu >> c)) - 1;
+                v = pk(run_key<D>(sh, l - 1, c, ce), baseu + popc64(below) - 1u);
+            } else {
+                v = pk(run_key<D>(sh, l, s0, e), id);
+            }
+            sh.P[id] = v;
         }
     }
     __syncthreads();
@@ -365,40 +369,52 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
     }
     __syncthreads();
 
-    // Refinement: unite the runs of every remaining adjacency between this
-    // line and the one above.  The adjacencies are enumerated bitwise from
-    // the two facing rows (lower = this line's top row T, upper = the line
-    // above's bottom row B); an edge is dropped when an edge further left
-    // joins the same two runs (consecutive foreground pixels of one row lie
-    // in one run), which leaves one edge per touching pair of runs:
-    //   4-connectivity: starts of the stretches of T & B;
+    // Refinement: unite the runs of every adjacency between this line and the
+    // one above that the coarse links do not already hold.  Adjacencies are
+    // enumerated bitwise from the two facing rows (lower = this line's top
+    // row T, upper = the line above's bottom row B); an edge is dropped when
+    // an edge further left joins the same two runs (consecutive foreground
+    // pixels of one row lie in one run), which leaves one edge per touching
+    // pair of runs:
+    //   4-connectivity: starts of the stretches of T & B (edge (i, i));
     //   8-connectivity: (i,i)   where neither side continues from i-1,
     //                   (i-1,i) where B does not continue from i-1,
     //                   (i,i-1) where T does not continue from i-1.
+    // Each run's first surviving edge, ordered by lower then upper pixel,
+    // joins it to the run holding its leftmost upper neighbour: that is its
+    // coarse link, so it is masked out.  The first edge position of every
+    // run is found for all runs at once: adding the run starts to the
+    // columns without an edge carries each start up to its first edge.
     if (l > 0) {
         const uint64_t T = top_row<D>(sh, l), B = bottom_row<D>(sh, l - 1);
+        const uint64_t lsl = sh.LS[l], lsu = sh.LS[l - 1];
+        const uint32_t basel = sh.base[l], baseu = sh.base[l - 1];
+        uint64_t c0, c1 = 0, c2 = 0;
         if (!D) {
             const uint64_t o = T & B;
-            for (uint64_t r = o & ~(o << 1) & wmask; r; r &= r - 1) {
-                const int i = ctz64(r);
-                punion(sh.P, run_id<D>(sh, l, i), run_id<D>(sh, l - 1, i));
-            }
+            const uint64_t e0 = o & ~(o << 1);
+            const uint64_t q = lm & ~e0;
+            const uint64_t first = (lsl & e0) | ((q + (lsl & q)) & e0);
+            c0 = e0 & ~first & wmask;
         } else {
             const uint64_t e0 = T & B & ~(T << 1) & ~(B << 1);
-            const uint64_t e1 = (T << 1) & B & ~(B << 1);
+            const uint64_t e1 = (T << 1) & B & ~(B << 1);  // index = upper pixel
             const uint64_t e2 = T & (B << 1) & ~(T << 1);
-            for (uint64_t r = e0 & wmask; r; r &= r - 1) {
-                const int i = ctz64(r);
-                punion(sh.P, run_id<D>(sh, l, i), run_id<D>(sh, l - 1, i));
-            }
-            for (uint64_t r = e1 & wmask; r; r &= r - 1) {
-                const int i = ctz64(r);
-                punion(sh.P, run_id<D>(sh, l, i - 1), run_id<D>(sh, l - 1, i));
-            }
-            for (uint64_t r = e2 & wmask; r; r &= r - 1) {
-                const int i = ctz64(r);
-                punion(sh.P, run_id<D>(sh, l, i), run_id<D>(sh, l - 1, i - 1));
-            }
+            const uint64_t x = e0 | e2 | (e1 >> 1);         // lower pixels with an edge
+            const uint64_t q = lm & ~x;
+            const uint64_t first = (lsl & x) | ((q + (lsl & q)) & x);
+            c0 = e0 & ~(first & e0) & wmask;
+            c2 = e2 & ~(first & e2) & wmask;
+            c1 = e1 & ~((first & ~e0 & ~e2) << 1) & wmask;
+        }
+        for (uint64_t r = c0 | c1 | c2; r; r &= r - 1) {
+            const int i = ctz64(r);
+            const uint64_t bit = 1ull << i;
+            const uint32_t lo_i = basel + popc64(lsl & upto(i)) - 1u;
+            const uint32_t up_i = baseu + popc64(lsu & upto(i)) - 1u;
+            if (c0 & bit) punion(sh.P, lo_i, up_i);
+            if (D && (c1 & bit)) punion(sh.P, basel + popc64(lsl & upto(i - 1)) - 1u, up_i);
+            if (D && (c2 & bit)) punion(sh.P, lo_i, baseu + popc64(lsu & upto(i - 1)) - 1u);
         }
     }
     __syncthreads();
@@ -467,9 +483,18 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
 }
 
 // ---------------------------------------------------------------------------
-// k_seam
+// block merge (Section 3.2), in two levels
 // ---------------------------------------------------------------------------
-
+//
+// The paper merges blocks by inspecting only the pixels on block borders
+// (Eq. 1-2: the candidates shrink by the block width along each axis).  The
+// same boundary analysis runs here at two scales:
+//   k_block  one workgroup per group of BX x BY tiles unites, in LDS, the
+//            border components of its tiles across the seams inside the
+//            group, then writes every component's group root into the HBM
+//            forest (plain stores: no other workgroup touches those nodes);
+//   k_seam   the seams between groups, united in the HBM forest with atomics.
+//
 // Along a seam, A[k] / B[k] are the node ids of the pixels at seam index k on
 // the first / second side (-1 = background).  Work item i owns the edges
 // whose larger index is i: (i, i) and, with diagonals, (i-1, i) and (i, i-1).
@@ -482,64 +507,221 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
 //   (i-1, i) is covered by (i-1, i-1) when B[i-1] == B[i];
 //   (i, i-1) is covered by (i-1, i-1) when A[i-1] == A[i].
 // For 4-connectivity only (i, i) exists, covered by (i-1, i-1) when both
-// sides repeat.
-template <int D>
-__device__ __forceinline__ void seam_item(uint64_t* F, int32_t a_prev, int32_t a,
-                                          int32_t b_prev, int32_t b)
+// sides repeat.  Node ids are unique across tiles, so a covering edge always
+// joins the same two tiles as the edge it covers.
+
+constexpr int BX = 4, BY = 4;                    // tiles per merge group
+constexpr int BPX = BX * TW, BPY = BY * TILE_ROWS;  // group size in pixels
+constexpr int BN = BX * BY * NSLOTS;             // border slots per group
+static_assert(BPX * BPY <= 65536 && BN <= 65536, "16-bit group keys and ids");
+
+// q = v / d, r = v % d for a runtime divisor, from magic = floor(2^32 / d)
+// (0xffffffff for d = 1): the estimate is low by at most two.
+__device__ __forceinline__ void divmod_w(uint32_t v, uint32_t d, uint32_t magic, uint32_t& q,
+                                         uint32_t& r)
 {
-    const bool ra = a_prev == a, rb = b_prev == b;
+    q = __umulhi(v, magic);
+    r = v - q * d;
+    while (r >= d) { ++q; r -= d; }
+}
+
+enum { E_II = 1, E_PI = 2, E_IP = 4 };  // edges (i,i), (i-1,i), (i,i-1)
+constexpr int SEAM_HASH = 512;           // pair table per k_seam workgroup (power of two)
+
+// Which of the three edges at seam index i survive the deduplication above.
+template <int D>
+__device__ __forceinline__ int seam_edges(int32_t ap, int32_t ac, int32_t bp, int32_t bc)
+{
+    const bool ra = ap == ac, rb = bp == bc;
+    int m = 0;
     if (D == 0) {
-        if (a >= 0 && b >= 0 && !(ra && rb)) g_union(F, (uint32_t)a, (uint32_t)b);
+        if (ac >= 0 && bc >= 0 && !(ra && rb)) m |= E_II;
     } else {
-        if (a >= 0 && b >= 0 && !ra && !rb) g_union(F, (uint32_t)a, (uint32_t)b);
-        if (a_prev >= 0 && b >= 0 && !rb) g_union(F, (uint32_t)a_prev, (uint32_t)b);
-        if (a >= 0 && b_prev >= 0 && !ra) g_union(F, (uint32_t)a, (uint32_t)b_prev);
+        if (ac >= 0 && bc >= 0 && !ra && !rb) m |= E_II;
+        if (ap >= 0 && bc >= 0 && !rb) m |= E_PI;
+        if (ac >= 0 && bp >= 0 && !ra) m |= E_IP;
+    }
+    return m;
+}
+
+// Node ids at seam index i-1 and i of a horizontal seam (tile rows k-1 | k)
+// at image column x, or of a vertical seam (tile columns j-1 | j) at image
+// row y (index i = row within the tile row; i-1 < 0 gives -1).
+struct SeamNodes {
+    int32_t ap, ac, bp, bc;
+};
+
+__device__ __forceinline__ SeamNodes hseam_nodes(const ImageArgs& a, const int32_t* slots, int k,
+                                                 int x)
+{
+    const int64_t top = (int64_t)(k - 1) * a.ntx, bot = (int64_t)k * a.ntx;
+    SeamNodes n;
+    n.ac = slots[(top + x / TW) * NSLOTS + TW + x % TW];
+    n.bc = slots[(bot + x / TW) * NSLOTS + x % TW];
+    n.ap = n.bp = -1;
+    if (x > 0) {
+        const int xp = x - 1;
+        n.ap = slots[(top + xp / TW) * NSLOTS + TW + xp % TW];
+        n.bp = slots[(bot + xp / TW) * NSLOTS + xp % TW];
+    }
+    return n;
+}
+
+__device__ __forceinline__ SeamNodes vseam_nodes(const ImageArgs& a, const int32_t* slots, int j,
+                                                 int y)
+{
+    const int k = y / TILE_ROWS, yl = y - k * TILE_ROWS;
+    const int32_t* left = slots + ((int64_t)k * a.ntx + j - 1) * NSLOTS + 2 * TW + TILE_ROWS;
+    const int32_t* right = slots + ((int64_t)k * a.ntx + j) * NSLOTS + 2 * TW;
+    SeamNodes n;
+    n.ac = left[yl];
+    n.bc = right[yl];
+    n.ap = yl > 0 ? left[yl - 1] : -1;
+    n.bp = yl > 0 ? right[yl - 1] : -1;
+    return n;
+}
+
+// Group-local index of a node: (tile within group) * NSLOTS + slot.  The
+// tile is given by its image tile coordinates.
+__device__ __forceinline__ uint32_t group_idx(int32_t node, int tx, int ty, int tx0, int ty0,
+                                              int ntx)
+{
+    const int32_t slot = node - (int32_t)(((int64_t)ty * ntx + tx) * NSLOTS);
+    return (uint32_t)(((ty - ty0) * BX + (tx - tx0)) * NSLOTS + slot);
+}
+
+constexpr int NTB = 1024;  // threads per merge-group workgroup
+
+template <int D>
+__global__ __launch_bounds__(NTB) void k_block(ImageArgs a, Workspace ws)
+{
+    __shared__ uint32_t P[BN];         // (group key << 16) | group index
+    __shared__ uint32_t isrep[BN / 32];  // group indices that are forest nodes
+    const int tid = threadIdx.x;
+    const int nbx = (a.ntx + BX - 1) / BX;
+    const int tx0 = (blockIdx.x % nbx) * BX, ty0 = (blockIdx.x / nbx) * BY;
+    const int px0 = tx0 * TW, py0 = ty0 * TILE_ROWS;
+
+    for (int i = tid; i < BN / 32; i += NTB) isrep[i] = 0u;
+    __syncthreads();
+    // nodes of the group, keyed by the position of their smallest pixel
+    // relative to the group origin (same order as raster position)
+    for (int li = tid; li < BN; li += NTB) {
+        const int ti = li / NSLOTS, sl = li % NSLOTS;
+        const int tx = tx0 + ti % BX, ty = ty0 + ti / BX;
+        if (tx >= a.ntx || ty >= a.nty) continue;
+        const int64_t node = ((int64_t)ty * a.ntx + tx) * NSLOTS + sl;
+        if (ws.slots[node] != (int32_t)node) continue;
+        uint32_t gy, gx;
+        divmod_w((uint32_t)(ws.forest[node] >> 32), (uint32_t)a.W, a.wmagic, gy, gx);
+        P[li] = pk((gy - py0) * BPX + (gx - px0), li);
+        atomicOr(isrep + (li >> 5), 1u << (li & 31));
+    }
+    __syncthreads();
+
+    // seams between tile columns inside the group
+    for (int it = tid; it < (BX - 1) * BPY; it += NTB) {
+        const int j = it / BPY + 1, y = py0 + it % BPY;
+        const int txr = tx0 + j;
+        if (txr >= a.ntx || y >= a.H) continue;
+        const int ty = y / TILE_ROWS;
+        const SeamNodes n = vseam_nodes(a, ws.slots, txr, y);
+        const int m = seam_edges<D>(n.ap, n.ac, n.bp, n.bc);
+        if (!m) continue;
+        auto L = [&](int32_t node) { return group_idx(node, txr - 1, ty, tx0, ty0, a.ntx); };
+        auto R = [&](int32_t node) { return group_idx(node, txr, ty, tx0, ty0, a.ntx); };
+        if (m & E_II) punion(P, L(n.ac), R(n.bc));
+        if (m & E_PI) punion(P, L(n.ap), R(n.bc));
+        if (m & E_IP) punion(P, L(n.ac), R(n.bp));
+    }
+    // seams between tile rows inside the group; diagonal edges that reach the
+    // group to the left belong to k_seam
+    for (int it = tid; it < (BY - 1) * BPX; it += NTB) {
+        const int k = ty0 + it / BPX + 1, x = px0 + it % BPX;
+        if (k >= a.nty || x >= a.W) continue;
+        const SeamNodes n = hseam_nodes(a, ws.slots, k, x);
+        int m = seam_edges<D>(n.ap, n.ac, n.bp, n.bc);
+        if (x == px0) m &= E_II;
+        if (!m) continue;
+        const int tx = x / TW, txp = (x - 1) / TW;
+        auto T0 = [&](int32_t node, int txx) { return group_idx(node, txx, k - 1, tx0, ty0, a.ntx); };
+        auto B0 = [&](int32_t node, int txx) { return group_idx(node, txx, k, tx0, ty0, a.ntx); };
+        if (m & E_II) punion(P, T0(n.ac, tx), B0(n.bc, tx));
+        if (m & E_PI) punion(P, T0(n.ap, txp), B0(n.bc, tx));
+        if (m & E_IP) punion(P, T0(n.ac, tx), B0(n.bp, txp));
+    }
+    __syncthreads();
+
+    // every node of the group now points at its group root
+    for (int li = tid; li < BN; li += NTB) {
+        if (!((isrep[li >> 5] >> (li & 31)) & 1u)) continue;
+        const uint32_t r = pfind(P, (uint32_t)li);
+        const uint32_t rl = pk_id(r), rk = pk_key(r);
+        auto node_of = [&](uint32_t l) {
+            const int ti = (int)(l / NSLOTS), sl = (int)(l % NSLOTS);
+            return (uint32_t)(((int64_t)(ty0 + ti / BX) * a.ntx + tx0 + ti % BX) * NSLOTS + sl);
+        };
+        const uint32_t gkey = (uint32_t)((int64_t)(py0 + (int)(rk / BPX)) * a.W + px0 + (int)(rk % BPX));
+        ws.forest[node_of((uint32_t)li)] = ((uint64_t)gkey << 32) | node_of(rl);
     }
 }
 
-// Block merge with boundary analysis (Section 3.2): only border pixels are
-// visited — (ntx-1)*H + (nty-1)*W work items, the paper's P_x + P_y of Eq. 1-2.
-// Horizontal seams (between tile rows) run over the full image width, so
-// diagonal pairs through a four-tile corner are seen there; vertical seams
-// (between tile columns) stay inside one tile row.
+// Seams between merge groups, united in the HBM forest.  Work items: every
+// position of the horizontal seams on group rows, of the vertical seams on
+// group columns, and (8-connectivity) the two diagonal edges that cross a
+// group column at each seam between tile rows inside a group.
 template <int D>
 __global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
 {
-    constexpr int NS = NSLOTS;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nh = (int64_t)(a.nty - 1) * a.W;
-    const int64_t nv = (int64_t)(a.ntx - 1) * a.H;
-    const int32_t* slots = ws.slots;
-
-    int32_t a_prev = -1, a_cur, b_prev = -1, b_cur;
+    const int nkh = (a.nty - 1) / BY, nkv = (a.ntx - 1) / BX;
+    const int nbx = (a.ntx + BX - 1) / BX;
+    const int64_t nh = (int64_t)nkh * a.W, nv = (int64_t)nkv * a.H;
+    const int64_t nc = D ? (int64_t)(a.nty - 1 - nkh) * (nbx - 1) : 0;
+    SeamNodes n;
+    int m;
     if (gid < nh) {
-        const int k = (int)(gid / a.W) + 1;
-        const int x = (int)(gid - (int64_t)(k - 1) * a.W);
-        const int64_t top = (int64_t)(k - 1) * a.ntx, bot = (int64_t)k * a.ntx;
-        a_cur = slots[(top + x / TW) * NS + TW + x % TW];
-        b_cur = slots[(bot + x / TW) * NS + x % TW];
-        if (x > 0) {
-            const int xp = x - 1;
-            a_prev = slots[(top + xp / TW) * NS + TW + xp % TW];
-            b_prev = slots[(bot + xp / TW) * NS + xp % TW];
-        }
+        n = hseam_nodes(a, ws.slots, (int)(gid / a.W + 1) * BY, (int)(gid % a.W));
+        m = seam_edges<D>(n.ap, n.ac, n.bp, n.bc);
     } else if (gid < nh + nv) {
         const int64_t g = gid - nh;
-        const int j = (int)(g / a.H) + 1;
-        const int y = (int)(g - (int64_t)(j - 1) * a.H);
-        const int k = y / TILE_ROWS, yl = y - k * TILE_ROWS;
-        const int64_t left = ((int64_t)k * a.ntx + j - 1) * NS + 2 * TW + TILE_ROWS;
-        const int64_t right = ((int64_t)k * a.ntx + j) * NS + 2 * TW;
-        a_cur = slots[left + yl];
-        b_cur = slots[right + yl];
-        if (yl > 0) {
-            a_prev = slots[left + yl - 1];
-            b_prev = slots[right + yl - 1];
-        }
+        n = vseam_nodes(a, ws.slots, (int)(g / a.H + 1) * BX, (int)(g % a.H));
+        m = seam_edges<D>(n.ap, n.ac, n.bp, n.bc);
+    } else if (gid < nh + nv + nc) {
+        const int64_t g = gid - nh - nv;
+        const int kk = (int)(g / (nbx - 1));
+        const int k = kk + kk / (BY - 1) + 1;  // skip tile rows that start a group
+        const int x = (int)(g % (nbx - 1) + 1) * BPX;
+        n = hseam_nodes(a, ws.slots, k, x);
+        m = seam_edges<D>(n.ap, n.ac, n.bp, n.bc) & (E_PI | E_IP);
     } else {
-        return;
+        m = 0;
+        n.ap = n.ac = n.bp = n.bc = -1;
     }
-    seam_item<D>(ws.forest, a_prev, a_cur, b_prev, b_cur);
+    // Replace each node by its current parent (after k_block: its group root),
+    // then drop pairs another item of this workgroup already holds: along a
+    // seam most foreground stretches join the same two group roots, and one
+    // union per distinct pair is enough.  A full table only costs duplicates.
+    __shared__ unsigned long long seen[SEAM_HASH];
+    for (int i = threadIdx.x; i < SEAM_HASH; i += blockDim.x) seen[i] = ~0ull;
+    __syncthreads();
+    uint64_t* F = ws.forest;
+    auto parent = [&](int32_t node) { return (uint32_t)g_ld(F + node); };
+    auto unite = [&](uint32_t x, uint32_t y) {
+        if (x == y) return;
+        if (x > y) { uint32_t t = x; x = y; y = t; }
+        const unsigned long long key = ((unsigned long long)x << 32) | y;
+        uint32_t h = (x * 0x9e3779b1u) ^ (y * 0x85ebca77u);
+        for (int probe = 0; probe < 8; ++probe, ++h) {
+            const unsigned long long prev = atomicCAS(seen + (h & (SEAM_HASH - 1)), ~0ull, key);
+            if (prev == key) return;         // already united by this workgroup
+            if (prev == ~0ull) break;        // claimed a fresh entry
+        }
+        g_union(F, x, y);
+    };
+    if (m & E_II) unite(parent(n.ac), parent(n.bc));
+    if (m & E_PI) unite(parent(n.ap), parent(n.bc));
+    if (m & E_IP) unite(parent(n.ac), parent(n.bp));
 }
 
 // ---------------------------------------------------------------------------
@@ -573,10 +755,14 @@ __global__ __launch_bounds__(NT) void k_final(ImageArgs a, Workspace ws)
     const int64_t sbase = (int64_t)t * NSLOTS;
 
     // global root of each border component, looked up once (by its root run)
-    for (uint32_t id = tid; id < R; id += NT) {
-        const uint16_t e = rt[id];
-        if ((e & (RT_BORDER | RT_ROOT)) == (RT_BORDER | RT_ROOT)) {
-            const int rep = e & 0x3fff;
+    constexpr int PER = (Geo<D>::MAXR + NT - 1) / NT;  // run-table entries per thread
+    uint16_t ent[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t id = tid + k * NT;
+        ent[k] = id < R ? rt[id] : (uint16_t)0;
+        if (id < R && (ent[k] & (RT_BORDER | RT_ROOT)) == (RT_BORDER | RT_ROOT)) {
+            const int rep = ent[k] & 0x3fff;
             const uint32_t key = LOCAL_ONLY
                                      ? (uint32_t)(g_ld(ws.forest + sbase + rep) >> 32)
                                      : g_find_ro(ws.forest, (uint32_t)(sbase + rep)).key;
@@ -584,16 +770,17 @@ __global__ __launch_bounds__(NT) void k_final(ImageArgs a, Workspace ws)
         }
     }
     __syncthreads();
-    for (uint32_t id = tid; id < R; id += NT) {
-        const uint16_t e = rt[id];
-        int32_t v;
-        if (e & RT_BORDER) {
-            v = sh.fin[e & 0x3fff];
-        } else {
-            // ID conversion of an interior component's local root
-            v = (int32_t)((int64_t)(gy0 + e / TW) * a.W + gx0 + e % TW + 1);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t id = tid + k * NT;
+        if (id < R) {
+            const uint16_t e = ent[k];
+            // border component: its global root; otherwise ID conversion of
+            // the interior component's local root
+            sh.lab[id] = (e & RT_BORDER)
+                             ? sh.fin[e & 0x3fff]
+                             : (int32_t)((int64_t)(gy0 + e / TW) * a.W + gx0 + e % TW + 1);
         }
-        sh.lab[id] = v;
     }
     __syncthreads();
 
@@ -604,15 +791,16 @@ __global__ __launch_bounds__(NT) void k_final(ImageArgs a, Workspace ws)
         const int gy = gy0 + r;
         if (gy >= a.H || x0 >= xmax) continue;
         const int l = D ? r >> 1 : r;
-        const uint64_t mr = sh.M[r], ls = sh.LS[l];
+        const uint64_t ls = sh.LS[l];
+        const uint32_t m4 = (uint32_t)(sh.M[r] >> x0) & 15u;
+        const uint32_t s4 = (uint32_t)(ls >> x0) & 15u;
         uint32_t cnt = sh.base[l] + popc64(ls & ~(~0ull << x0));  // runs starting left of x0
         int32_t v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int x = x0 + k;
-            cnt += (uint32_t)((ls >> x) & 1ull);
+            cnt += (s4 >> k) & 1u;
             // a foreground pixel has its run start at or left of it, so cnt >= 1
-            v[k] = ((mr >> x) & 1ull) ? sh.lab[cnt ? cnt - 1 : 0] : 0;
+            v[k] = ((m4 >> k) & 1u) ? sh.lab[cnt ? cnt - 1 : 0] : 0;
         }
         int32_t* dst = a.labels + (int64_t)gy * a.W + gx0 + x0;
         if (a.vec_out && x0 + 4 <= xmax) {
@@ -654,7 +842,14 @@ static hipError_t launch_all(const ImageArgs& a, const Workspace& ws, hipStream_
         timer_end(timer, KIND_FINAL, st);
         return hipGetLastError();
     }
-    const int64_t items = (int64_t)(a.nty - 1) * a.W + (int64_t)(a.ntx - 1) * a.H;
+    const int nbx = (a.ntx + BX - 1) / BX, nby = (a.nty + BY - 1) / BY;
+    if (a.ntx > 1 || a.nty > 1) {
+        timer_begin(timer, KIND_BLOCK, st);
+        k_block<D><<<(unsigned)(nbx * nby), NTB, 0, st>>>(a, ws);
+        timer_end(timer, KIND_BLOCK, st);
+    }
+    const int64_t items = (int64_t)((a.nty - 1) / BY) * a.W + (int64_t)((a.ntx - 1) / BX) * a.H +
+                          (D ? (int64_t)(a.nty - 1 - (a.nty - 1) / BY) * (nbx - 1) : 0);
     if (items > 0) {
         timer_begin(timer, KIND_SEAM, st);
         k_seam<D><<<(unsigned)((items + 255) / 256), 256, 0, st>>>(a, ws);

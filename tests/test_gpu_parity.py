@@ -88,6 +88,31 @@ def test_seam_patterns(ccl, conn):
 
 
 @pytest.mark.parametrize("conn", [4, 8])
+def test_group_seam_patterns(ccl, conn):
+    """Random 4x4 patterns on every kind of seam of a multi-group image: tile
+    seams, seams between merge groups (every 4 tiles), group corners, and the
+    diagonals that cross a group column on a tile seam inside a group."""
+    rows, cols = ccl.tile_shape()
+    gr, gc = 4 * rows, 4 * cols
+    rng = np.random.default_rng(100 + conn)
+    H, W = 2 * gr + 3 * rows, 2 * gc + 2 * cols + 5
+    centres = [(y, x) for y in range(rows, H, rows) for x in range(cols, W, cols)]
+    for trial in range(12):
+        img = (rng.random((H, W)) < 0.04).astype(np.uint8)
+        for cy, cx in centres:
+            img[cy - 2:cy + 2, cx - 2:cx + 2] = rng.random((4, 4)) < 0.5
+        assert_parity(ccl, img, conn, f"group seam trial {trial}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("H,W", [(1000, 1000), (257, 1030), (1030, 257), (64 * 9, 64 * 9),
+                                 (64 * 8 + 1, 64 * 8 - 1)])
+def test_multi_group_random(ccl, H, W, conn):
+    for p in (0.45, 0.6):
+        assert_parity(ccl, wl.bernoulli(H, W, p, seed=H + 7 * W), conn, f"bernoulli{p}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
 def test_values_pitch_alignment(ccl, conn):
     img = wl.bernoulli(150, 200, 0.5, seed=11)
     want = oracle_label(img, conn)
