@@ -34,8 +34,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 PATH_BYTES_PER_PX = 5.0        # 1 B read + 4 B written: the minimum for the path
-FINAL_BYTES_PER_PX = 4.0 + 1.0 / 8.0   # k_final: label write + bitmask read
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_final_4096.json")
+# algorithmic HBM bytes per pixel of each kernel: what it must move at least
+KERNEL_BYTES_PER_PX = {
+    "local": 1.0 + 1.0 / 8.0,   # image read + foreground bitmask write
+    "final": 4.0 + 1.0 / 8.0,   # label write + bitmask read
+}
+KERNEL_NAMES = {"local": "k_local", "block": "k_block", "seam": "k_seam", "final": "k_final"}
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_bench_4096.md")
 
 
 def kernel_source_hash() -> str:
@@ -60,8 +65,9 @@ def headline_cases(size):
     return cases
 
 
-def time_rotation(ccl, torch, devs, steps, warmup, timing=False):
-    """Label devs[i % n] for `steps` steps; returns (seconds, per-kernel dict)."""
+def time_rotation(ccl, torch, devs, steps, warmup, timing=None):
+    """Label devs[i % n] for `steps` steps; returns (seconds, per-kernel dict).
+    `timing` lists the kernel kinds to bracket with HIP events (None: none)."""
     st = torch.cuda.current_stream()
     n = len(devs)
     for i in range(warmup):
@@ -69,7 +75,7 @@ def time_rotation(ccl, torch, devs, steps, warmup, timing=False):
         ccl.label(img, conn, out=out)
     torch.cuda.synchronize()
     if timing:
-        ccl.timing_enable(True)
+        ccl.timing_enable(True, kinds=timing)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(st)
@@ -86,17 +92,94 @@ def time_rotation(ccl, torch, devs, steps, warmup, timing=False):
     return secs, kern
 
 
-def load_traffic(src_hash, px):
-    """HBM bytes per k_final launch from the committed rocprofv3 counter runs,
-    only if they were taken on the current kernel source."""
+def read_profile_fields(path):
+    """`key: value` lines of a profile summary."""
+    out = {}
     try:
-        with open(PROFILE_TRAFFIC) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(("#", "|", " ", "`")):
+                    k, v = line.split(":", 1)
+                    out[k.strip()] = v.strip()
+    except OSError:
+        pass
+    return out
+
+
+def load_traffic(src_hash, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs, only if they were taken on the current kernel source."""
+    rec = read_profile_fields(PROFILE_TRAFFIC)
+    key = f"{kernel}_bytes_per_launch"
+    if rec.get("kernel_source_hash") != src_hash or key not in rec:
         return None
-    if rec.get("kernel_source_hash") != src_hash:
-        return None
-    return rec.get("bytes_per_launch")
+    return float(rec[key])
+
+
+def _short_kernel(name):
+    import re
+    m = re.search(r"ccl::(k_\w+)(<[^>(]*>)?", name)
+    return (m.group(1) + (m.group(2) or "")) if m else name[:48]
+
+
+def summarize_trace(db, out, cmd):
+    """Kernel-trace database -> markdown table of per-kernel durations."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration), "
+                       "sum(duration) from kernels group by name").fetchall()
+    rows = sorted(rows, key=lambda r: -r[5])
+    lines = ["# Kernel trace: " + os.path.basename(out).rsplit(".", 1)[0], "",
+             "Produced by:", "", "```", cmd, "```", "",
+             f"kernel_source_hash: {kernel_source_hash()}", "",
+             "| kernel | launches | avg us | min us | max us | total ms |",
+             "|---|---|---|---|---|---|"]
+    for name, n, avg, mn, mx, tot in rows:
+        lines.append(f"| {_short_kernel(name)} | {n} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | "
+                     f"{mx / 1e3:.2f} | {tot / 1e6:.3f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _counter_mean(db, kernel_sub, counter):
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                       "where counter_name = ? group by dispatch_id", (counter,)).fetchall()
+    vals = [v for k, d, v in rows if kernel_sub in k]
+    return sum(vals) / len(vals), len(vals)
+
+
+def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes, out, cmd,
+                      px=4096 * 4096):
+    """FETCH_SIZE / WRITE_SIZE runs of the labelling kernels, scaled by what the
+    same counters read for the copy kernel over a known number of bytes."""
+    cf_kib, _ = _counter_mean(copy_fetch_db, "k_copy", "FETCH_SIZE")
+    cw_kib, _ = _counter_mean(copy_write_db, "k_copy", "WRITE_SIZE")
+    ff = copy_bytes / (cf_kib * 1024.0)
+    wf = copy_bytes / (cw_kib * 1024.0)
+    lines = ["# HBM traffic per launch on the 4096x4096 headline workload", "",
+             "Produced by (each counter in its own run):", "", "```", cmd, "```", "",
+             f"kernel_source_hash: {kernel_source_hash()}",
+             f"copy_bytes: {copy_bytes}",
+             f"copy_fetch_kib: {cf_kib:.1f}",
+             f"copy_write_kib: {cw_kib:.1f}",
+             f"fetch_factor: {ff:.4f}",
+             f"write_factor: {wf:.4f}", "",
+             "| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes | algorithmic bytes |",
+             "|---|---|---|---|---|---|"]
+    fields = []
+    for kind, kname in KERNEL_NAMES.items():
+        f_kib, nf = _counter_mean(fetch_db, kname, "FETCH_SIZE")
+        w_kib, nw = _counter_mean(write_db, kname, "WRITE_SIZE")
+        total = f_kib * 1024.0 * ff + w_kib * 1024.0 * wf
+        algo = KERNEL_BYTES_PER_PX.get(kind, 0.0) * px
+        lines.append(f"| {kname} | {nf} | {f_kib:.1f} | {w_kib:.1f} | {total:.0f} | "
+                     f"{algo:.0f} |")
+        fields.append(f"{kind}_bytes_per_launch: {total:.0f}")
+    lines += [""] + fields + [""]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def main():
@@ -109,7 +192,21 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel over MIB MiB (counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"),
+                    help="write a rocprofv3 kernel-trace summary (no GPU needed)")
+    ap.add_argument("--summarize-traffic", nargs=7,
+                    metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB",
+                             "COPY_BYTES", "OUT", "CMD"),
+                    help="write the k_final HBM traffic summary (no GPU needed)")
     args = ap.parse_args()
+
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        a = args.summarize_traffic
+        summarize_traffic(a[0], a[1], a[2], a[3], int(a[4]), a[5], a[6])
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -176,22 +273,28 @@ def main():
                "sample": f"{len(cases)} images of {size}x{size} (every headline case once), "
                          f"single thread pinned to one core, {cpu_secs:.1f} s total"}
 
-    # timed region (headline value) and a second, event-instrumented region
-    # for the per-kernel durations behind the roofline figure
+    # timed region (headline value); then a region with events around every
+    # kernel (per-kernel breakdown) and one with events around the dominant
+    # kernel only (its duration, for the roofline figure)
     secs, _ = time_rotation(ccl, torch, devs, args.steps, args.warmup)
-    secs_i, kern = time_rotation(ccl, torch, devs, args.steps, args.warmup, timing=True)
+    secs_all, kern = time_rotation(ccl, torch, devs, args.steps, args.warmup,
+                                   timing=["local", "block", "seam", "final"])
+    kavg = {k: round(1e3 * v[0] / v[1], 2) for k, v in kern.items() if v[1]}
+    dom = max(("local", "final"), key=lambda k: kavg.get(k, 0.0))
+    _, kdom = time_rotation(ccl, torch, devs, args.steps, args.warmup, timing=[dom])
     px = size * size
     value = args.steps * px / secs / 1e9
     ms_step = 1e3 * secs / args.steps
     log(f"[bench] {size}^2: {value:.1f} Gpx/s, {ms_step * 1e3:.1f} us/step "
-        f"(instrumented {1e6 * secs_i / args.steps:.1f} us/step); kernels {kern}")
+        f"(events around every kernel: {1e6 * secs_all / args.steps:.1f} us/step); "
+        f"kernel avg us {kavg}")
 
-    fin_ms, fin_n = kern["final"]
-    fin_avg_s = fin_ms / fin_n / 1e3
-    achieved = FINAL_BYTES_PER_PX * px / fin_avg_s / 1e9
+    dom_ms, dom_n = kdom[dom]
+    dom_avg_s = dom_ms / dom_n / 1e3
+    algo_bytes = KERNEL_BYTES_PER_PX[dom] * px
+    achieved = algo_bytes / dom_avg_s / 1e9
     src_hash = kernel_source_hash()
-    traffic = load_traffic(src_hash, px)
-    kavg = {k: round(1e3 * v[0] / v[1], 2) for k, v in kern.items() if v[1]}
+    traffic = load_traffic(src_hash, dom)
 
     result = {
         "metric": "Gpixel/s at 4096^2 (exact vs oracle)",
@@ -213,12 +316,12 @@ def main():
                    "tile": list(ccl.tile_shape())},
         "path_hbm_frac": round(PATH_BYTES_PER_PX * value / HBM_PEAK_GBS, 4),
         "kernel_avg_us": kavg,
-        "roofline": {"bound": "hbm", "kernel": "k_final",
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": FINAL_BYTES_PER_PX * px,
-                     "avg_launch_us": round(fin_avg_s * 1e6, 2)},
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "avg_launch_us": round(dom_avg_s * 1e6, 2)},
         "cpu_baseline": cpu,
     }
 

@@ -112,11 +112,12 @@ int ccl_release_workspace(int32_t device);
 
 /*
  * Per-kernel timing with HIP events recorded on the launch stream.
- * ccl_timing_enable(1) clears the counters and starts recording around every
- * kernel the library launches; ccl_timing_read() waits for the recorded
- * events and fills, for each kernel kind k < n (0 = local step, 1 = merge
- * across tile groups, 2 = final relabel, 3 = copy, 4 = merge inside tile
- * groups), the summed milliseconds ms[k] and launch count launches[k].
+ * ccl_timing_enable(mask) clears the counters and starts recording events
+ * around every kernel of the kinds whose bit is set in `mask` (bit k = kind
+ * k; 0 stops recording).  Kinds: 0 = local step, 1 = merge across tile
+ * groups, 2 = final relabel, 3 = copy, 4 = merge inside tile groups.
+ * ccl_timing_read() waits for the recorded events and fills, for each kind
+ * k < n, the summed milliseconds ms[k] and launch count launches[k].
  * Returns the number of kinds (5).
  */
 int ccl_timing_enable(int32_t enable);

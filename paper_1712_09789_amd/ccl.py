@@ -161,8 +161,15 @@ def release_workspace(device: int = 0) -> None:
     _check(_lib.ccl_release_workspace(device))
 
 
-def timing_enable(on: bool = True) -> None:
-    _check(_lib.ccl_timing_enable(1 if on else 0))
+def timing_enable(on: bool = True, kinds=None) -> None:
+    """Record HIP events around the kernels named in `kinds` (all when None)."""
+    if not on:
+        mask = 0
+    elif kinds is None:
+        mask = (1 << len(KERNEL_KINDS)) - 1
+    else:
+        mask = sum(1 << KERNEL_KINDS.index(k) for k in kinds)
+    _check(_lib.ccl_timing_enable(mask))
 
 
 def timing_read() -> dict:

@@ -109,11 +109,11 @@ struct KernelTimer {
 };
 
 static KernelTimer g_timer;
-static bool g_timing = false;
+static uint32_t g_timing_mask = 0;  // bit k: time kernel kind k
 
 void timer_begin(KernelTimer* t, int kind, hipStream_t st)
 {
-    if (!t) return;
+    if (!t || !((g_timing_mask >> kind) & 1u)) return;
     std::lock_guard<std::mutex> lk(t->mu);
     hipEvent_t e = t->take();
     if (e && hipEventRecord(e, st) == hipSuccess) t->open[kind] = e;
@@ -121,7 +121,7 @@ void timer_begin(KernelTimer* t, int kind, hipStream_t st)
 
 void timer_end(KernelTimer* t, int kind, hipStream_t st)
 {
-    if (!t) return;
+    if (!t || !((g_timing_mask >> kind) & 1u)) return;
     std::lock_guard<std::mutex> lk(t->mu);
     hipEvent_t a = t->open[kind];
     t->open[kind] = nullptr;
@@ -130,7 +130,7 @@ void timer_end(KernelTimer* t, int kind, hipStream_t st)
     if (b && hipEventRecord(b, st) == hipSuccess) t->done.push_back({kind, a, b});
 }
 
-static KernelTimer* active_timer() { return g_timing ? &g_timer : nullptr; }
+static KernelTimer* active_timer() { return g_timing_mask ? &g_timer : nullptr; }
 
 // ---------------------------------------------------------------------------
 // validation
@@ -285,7 +285,7 @@ int ccl_timing_enable(int32_t enable)
         g_timer.ms[k] = 0.0;
         g_timer.launches[k] = 0;
     }
-    g_timing = enable != 0;
+    g_timing_mask = (uint32_t)enable & ((1u << NKINDS) - 1u);
     return CCL_OK;
 }
 
