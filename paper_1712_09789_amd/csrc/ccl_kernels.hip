@@ -34,6 +34,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "ccl_kernels.h"
 
 namespace ccl {
@@ -48,6 +53,9 @@ struct Geo {
     static constexpr int TPL = NT / NL;                       // threads per line
     static constexpr int WIN = TW / TPL;                      // columns per thread
     static constexpr int MAXR = NL * (TW / 2);                // runs per tile, at most
+    // refinement edges per tile, at most: one per column and line boundary
+    // (8-connectivity), one per stretch start of T & B (4-connectivity)
+    static constexpr int MAXE = NL * (D ? TW : TW / 2);
 };
 static_assert(Geo<0>::MAXR <= RUNTAB_PER_TILE && Geo<1>::MAXR <= RUNTAB_PER_TILE, "run table");
 static_assert(NSLOTS == NT, "one border slot per thread");
@@ -255,11 +263,14 @@ __device__ __forceinline__ uint32_t run_key(const Lines<D>& sh, int l, int a, in
 
 template <int D>
 struct LocalShared : Lines<D> {
-    uint32_t P[Geo<D>::MAXR];
+    uint32_t P[Geo<D>::MAXR];    // parent of each run, packed (key << 16) | id
+    uint16_t RL[Geo<D>::MAXR];   // run record: start column | line << 6
+    uint32_t nedges;             // refinement edges listed so far
     union {
-        uint16_t h[TILE_ROWS * 4];  // 16-pixel masks as produced by the byte load
-        uint64_t w[TILE_ROWS];      // the same bits as one word per row
-    } m16;
+        uint32_t EL[Geo<D>::MAXE];     // refinement edge: lower run | upper run << 16
+        uint16_t h[TILE_ROWS * 4];     // 16-pixel masks as produced by the byte load
+        uint64_t w[TILE_ROWS];         // the same bits as one word per row
+    } u;
 };
 
 // Border slot s -> tile-local (x, y).  Slots: top row, bottom row, left
@@ -282,52 +293,68 @@ constexpr uint32_t REP_TAG = 0x80000000u;
 // k_local
 // ---------------------------------------------------------------------------
 
+// Initialisation (Section 3.1.1): sixteen bytes of a tile, four threads per
+// row.  Bytes past the image edge read as background.  The raw bytes are
+// returned so that the load of the next tile can be in flight while the
+// current one is labelled.
+__device__ __forceinline__ uint4 fetch_chunk(const ImageArgs& a, int t, int c)
+{
+    const int gx = (t % a.ntx) * TW + 16 * (c & 3);
+    const int gy = (t / a.ntx) * TILE_ROWS + (c >> 2);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gy < a.H && gx < a.W) {
+        const uint8_t* src = a.img + (int64_t)gy * a.pitch + gx;
+        if (a.vec_in && gx + 16 <= a.W) {
+            v = *reinterpret_cast<const uint4*>(src);
+        } else {
+            const int n = a.W - gx < 16 ? a.W - gx : 16;
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            for (int i = 0; i < n; ++i) w[i >> 2] |= (uint32_t)src[i] << (8 * (i & 3));
+            v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+    return v;
+}
+
+// Foreground bits of sixteen bytes (bit i = byte i != 0).
+__device__ __forceinline__ uint32_t chunk_mask(uint4 v)
+{
+    return nz_nibble(v.x) | (nz_nibble(v.y) << 4) | (nz_nibble(v.z) << 8) | (nz_nibble(v.w) << 12);
+}
+
+// The local step on tile t; sh.u.h holds its foreground bits on entry.
 template <int D>
-__global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
+__device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<D>& sh, int t,
+                           int tid)
 {
     using G = Geo<D>;
-    __shared__ LocalShared<D> sh;
-    const int tid = threadIdx.x;
-    const int t = blockIdx.x;
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
-    // Initialisation: load the tile's bytes, four threads per row, sixteen
-    // pixels per thread, and turn them into foreground bits.
-    for (int c = tid; c < TILE_ROWS * 4; c += NT) {
-        const int r = c >> 2, q = c & 3;
-        const int gy = gy0 + r, gx = gx0 + 16 * q;
-        uint32_t bits = 0;
-        if (gy < a.H && gx < a.W) {
-            const uint8_t* src = a.img + (int64_t)gy * a.pitch + gx;
-            if (a.vec_in && gx + 16 <= a.W) {
-                const uint4 v = *reinterpret_cast<const uint4*>(src);
-                bits = nz_nibble(v.x) | (nz_nibble(v.y) << 4) | (nz_nibble(v.z) << 8) |
-                       (nz_nibble(v.w) << 12);
-            } else {
-                const int n = a.W - gx < 16 ? a.W - gx : 16;
-                for (int i = 0; i < n; ++i) bits |= (uint32_t)(src[i] != 0) << i;
-            }
-        }
-        sh.m16.h[c] = (uint16_t)bits;
-    }
-    __syncthreads();
     if (tid < TILE_ROWS) {
-        const uint64_t m = sh.m16.w[tid];
+        const uint64_t m = sh.u.w[tid];
         sh.M[tid] = m;
         ws.bits[(int64_t)t * TILE_ROWS + tid] = m;
     }
     __syncthreads();
     build_lines<D>(sh, tid);
 
-    // This thread's line and column window; its runs are those starting in
-    // the window, with consecutive ids from id0.
-    const int l = tid / G::TPL;
-    const int wlo = (tid % G::TPL) * G::WIN;
-    const uint64_t wmask = (G::WIN == 64 ? ~0ull : ((1ull << G::WIN) - 1ull)) << wlo;
-    const uint64_t lm = sh.LM[l];
-    const uint64_t mine = sh.LS[l] & wmask;
-    const uint32_t id0 = sh.base[l] + popc64(sh.LS[l] & ~(~0ull << wlo));
+    // The heavy phases below walk dense run ids (thread tid takes ids tid,
+    // tid + 256, ...) so that every lane has work; only two cheap passes walk
+    // the bits of a column window: the run list and the refinement edge list.
+    const uint32_t R = sh.base[G::NL];
+    static_assert(G::WIN <= 16, "column windows fit a 32-bit word");
+    const int wl = tid / G::TPL;              // this thread's line
+    const int wlo = (tid % G::TPL) * G::WIN;  // and first column of its window
+    constexpr uint32_t WMASK = (1u << G::WIN) - 1u;
+    {
+        const uint64_t ls = sh.LS[wl];
+        uint32_t id = sh.base[wl] + popc64(ls & ~(~0ull << wlo));
+        for (uint32_t r = (uint32_t)(ls >> wlo) & WMASK; r; r &= r - 1u, ++id)
+            sh.RL[id] = (uint16_t)((__builtin_ctz(r) + wlo) | (wl << 6));
+    }
+    if (tid == 0) sh.nedges = 0u;
+    __syncthreads();
 
     // Row connection and column connection (coarse), one pass over the runs.
     // A run is a provisional label keyed by its smallest pixel (the paper's
@@ -335,47 +362,36 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
     // records the lowest label among its neighbours there instead, i.e. the
     // run holding the leftmost pixel of that line's facing row that touches
     // it.  One plain store per run: every entry is written by its owner only.
-    {
-        const uint64_t top = top_row<D>(sh, l);
-        const uint64_t up = l > 0 ? bottom_row<D>(sh, l - 1) : 0ull;
-        const uint64_t lsu = l > 0 ? sh.LS[l - 1] : 0ull;
-        const uint64_t lmu = l > 0 ? sh.LM[l - 1] : 0ull;
-        const uint32_t baseu = l > 0 ? sh.base[l - 1] : 0u;
-        uint32_t id = id0;
-        for (uint64_t r = mine; r; r &= r - 1, ++id) {
-            const int s0 = ctz64(r);
-            const int e = s0 + ctz64_or64(~(lm >> s0)) - 1;
-            const uint64_t mt = top & span_mask(s0, e);
+    for (uint32_t id = tid; id < R; id += NT) {
+        const uint32_t rec = sh.RL[id];
+        const int s0 = rec & 63, l = rec >> 6;
+        const uint64_t lm = sh.LM[l];
+        const int e = s0 + ctz64_or64(~(lm >> s0)) - 1;
+        uint32_t v = pk(run_key<D>(sh, l, s0, e), id);
+        if (l > 0) {
+            const uint64_t mt = top_row<D>(sh, l) & span_mask(s0, e);
             const uint64_t reach = D ? (mt | (mt << 1) | (mt >> 1)) : mt;
-            const uint64_t contact = up & reach;
-            uint32_t v;
+            const uint64_t contact = bottom_row<D>(sh, l - 1) & reach;
             if (contact) {
-                const uint64_t below = lsu & upto(ctz64(contact));
+                const uint64_t below = sh.LS[l - 1] & upto(ctz64(contact));
                 const int c = msb64(below);
-                const int ce = c + ctz64_or64(~(lmu >> c)) - 1;
-                v = pk(run_key<D>(sh, l - 1, c, ce), baseu + popc64(below) - 1u);
-            } else {
-                v = pk(run_key<D>(sh, l, s0, e), id);
+                const int ce = c + ctz64_or64(~(sh.LM[l - 1] >> c)) - 1;
+                v = pk(run_key<D>(sh, l - 1, c, ce), sh.base[l - 1] + popc64(below) - 1u);
             }
-            sh.P[id] = v;
         }
+        sh.P[id] = v;
     }
     __syncthreads();
 
     // Label-equivalence unification: every run points at its current root.
-    {
-        uint32_t id = id0;
-        for (uint64_t r = mine; r; r &= r - 1, ++id) lds_st(sh.P + id, pfind(sh.P, id));
-    }
-    __syncthreads();
+    for (uint32_t id = tid; id < R; id += NT) lds_st(sh.P + id, pfind(sh.P, id));
 
-    // Refinement: unite the runs of every adjacency between this line and the
-    // one above that the coarse links do not already hold.  Adjacencies are
-    // enumerated bitwise from the two facing rows (lower = this line's top
-    // row T, upper = the line above's bottom row B); an edge is dropped when
-    // an edge further left joins the same two runs (consecutive foreground
-    // pixels of one row lie in one run), which leaves one edge per touching
-    // pair of runs:
+    // Refinement edges: every adjacency between a line and the one above that
+    // the coarse links do not already hold.  They are enumerated bitwise from
+    // the two facing rows (lower = this line's top row T, upper = the line
+    // above's bottom row B); an edge is dropped when an edge further left
+    // joins the same two runs (consecutive foreground pixels of one row lie
+    // in one run), which leaves at most one edge per column:
     //   4-connectivity: starts of the stretches of T & B (edge (i, i));
     //   8-connectivity: (i,i)   where neither side continues from i-1,
     //                   (i-1,i) where B does not continue from i-1,
@@ -385,17 +401,20 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
     // coarse link, so it is masked out.  The first edge position of every
     // run is found for all runs at once: adding the run starts to the
     // columns without an edge carries each start up to its first edge.
-    if (l > 0) {
+    uint32_t cw = 0, c1w = 0, c2w = 0;  // edges in this thread's window (bit j = column wlo + j)
+    uint32_t lslw = 0, lsuw = 0;        // run starts of the two lines in the window
+    uint32_t prel = 0, preu = 0;        // runs of the two lines starting left of the window
+    if (wl > 0) {
+        const int l = wl;
         const uint64_t T = top_row<D>(sh, l), B = bottom_row<D>(sh, l - 1);
-        const uint64_t lsl = sh.LS[l], lsu = sh.LS[l - 1];
-        const uint32_t basel = sh.base[l], baseu = sh.base[l - 1];
+        const uint64_t lm = sh.LM[l], lsl = sh.LS[l], lsu = sh.LS[l - 1];
         uint64_t c0, c1 = 0, c2 = 0;
         if (!D) {
             const uint64_t o = T & B;
             const uint64_t e0 = o & ~(o << 1);
             const uint64_t q = lm & ~e0;
             const uint64_t first = (lsl & e0) | ((q + (lsl & q)) & e0);
-            c0 = e0 & ~first & wmask;
+            c0 = e0 & ~first;
         } else {
             const uint64_t e0 = T & B & ~(T << 1) & ~(B << 1);
             const uint64_t e1 = (T << 1) & B & ~(B << 1);  // index = upper pixel
@@ -403,27 +422,45 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
             const uint64_t x = e0 | e2 | (e1 >> 1);         // lower pixels with an edge
             const uint64_t q = lm & ~x;
             const uint64_t first = (lsl & x) | ((q + (lsl & q)) & x);
-            c0 = e0 & ~(first & e0) & wmask;
-            c2 = e2 & ~(first & e2) & wmask;
-            c1 = e1 & ~((first & ~e0 & ~e2) << 1) & wmask;
+            c0 = e0 & ~(first & e0);
+            c2 = e2 & ~(first & e2);
+            c1 = e1 & ~((first & ~e0 & ~e2) << 1);
         }
-        for (uint64_t r = c0 | c1 | c2; r; r &= r - 1) {
-            const int i = ctz64(r);
-            const uint64_t bit = 1ull << i;
-            const uint32_t lo_i = basel + popc64(lsl & upto(i)) - 1u;
-            const uint32_t up_i = baseu + popc64(lsu & upto(i)) - 1u;
-            if (c0 & bit) punion(sh.P, lo_i, up_i);
-            if (D && (c1 & bit)) punion(sh.P, basel + popc64(lsl & upto(i - 1)) - 1u, up_i);
-            if (D && (c2 & bit)) punion(sh.P, lo_i, baseu + popc64(lsu & upto(i - 1)) - 1u);
+        cw = (uint32_t)((c0 | c1 | c2) >> wlo) & WMASK;
+        c1w = (uint32_t)(c1 >> wlo) & WMASK;
+        c2w = (uint32_t)(c2 >> wlo) & WMASK;
+        lslw = (uint32_t)(lsl >> wlo) & WMASK;
+        lsuw = (uint32_t)(lsu >> wlo) & WMASK;
+        const uint64_t left = ~(~0ull << wlo);
+        prel = sh.base[l] + popc64(lsl & left) - 1u;
+        preu = sh.base[l - 1] + popc64(lsu & left) - 1u;
+    }
+    // At most one edge per column, so the edge count of the window is a
+    // popcount; edges go to the list in any order.
+    if (cw) {
+        uint32_t off = atomicAdd(&sh.nedges, (uint32_t)__builtin_popcount(cw));
+        for (uint32_t r = cw; r; r &= r - 1u, ++off) {
+            const int j = __builtin_ctz(r);
+            const uint32_t bit = 1u << j;
+            // run holding the lower / upper pixel: runs starting at or left of it
+            const int jl = (c1w & bit) ? j : j + 1;  // (i-1, i): lower pixel one left
+            const int ju = (c2w & bit) ? j : j + 1;  // (i, i-1): upper pixel one left
+            sh.u.EL[off] = (prel + __builtin_popcount(lslw & ((1u << jl) - 1u))) |
+                           ((preu + __builtin_popcount(lsuw & ((1u << ju) - 1u))) << 16);
         }
+    }
+    __syncthreads();
+    const uint32_t E = sh.nedges;
+
+    // Refinement: the paper's merge on every listed edge.
+    for (uint32_t k = tid; k < E; k += NT) {
+        const uint32_t ed = sh.u.EL[k];
+        punion(sh.P, ed & 0xffffu, ed >> 16);
     }
     __syncthreads();
 
     // Unification again: every run points straight at its final local root.
-    {
-        uint32_t id = id0;
-        for (uint64_t r = mine; r; r &= r - 1, ++id) lds_st(sh.P + id, pfind(sh.P, id));
-    }
+    for (uint32_t id = tid; id < R; id += NT) lds_st(sh.P + id, pfind(sh.P, id));
     __syncthreads();
 
     // Border slots (one per thread): local root of each border pixel.
@@ -464,21 +501,39 @@ __global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
 
     // Run table: interior components store their root's tile key; border
     // components store their representative slot (and mark the root run).
-    {
-        uint16_t* rt = ws.runtab + (int64_t)t * RUNTAB_PER_TILE;
-        uint32_t id = id0;
-        for (uint64_t r = mine; r; r &= r - 1, ++id) {
-            const uint32_t v = lds_ld(sh.P + id);
-            uint16_t ent;
-            if (v & REP_TAG) {
-                ent = (uint16_t)(RT_BORDER | RT_ROOT | (NSLOTS - 1 - pk_id(v)));
-            } else {
-                const uint32_t w = pk_id(v) == id ? v : lds_ld(sh.P + pk_id(v));
-                ent = (w & REP_TAG) ? (uint16_t)(RT_BORDER | (NSLOTS - 1 - pk_id(w)))
-                                    : (uint16_t)pk_key(v);
-            }
-            rt[id] = ent;
+    uint16_t* rt = ws.runtab + (int64_t)t * RUNTAB_PER_TILE;
+    for (uint32_t id = tid; id < R; id += NT) {
+        const uint32_t v = lds_ld(sh.P + id);
+        uint16_t ent;
+        if (v & REP_TAG) {
+            ent = (uint16_t)(RT_BORDER | RT_ROOT | (NSLOTS - 1 - pk_id(v)));
+        } else {
+            const uint32_t w = pk_id(v) == id ? v : lds_ld(sh.P + pk_id(v));
+            ent = (w & REP_TAG) ? (uint16_t)(RT_BORDER | (NSLOTS - 1 - pk_id(w)))
+                                : (uint16_t)pk_key(v);
         }
+        rt[id] = ent;
+    }
+}
+
+// Persistent over tiles: each workgroup labels tiles blockIdx.x, +gridDim.x,
+// ... and loads the next tile's bytes while labelling the current one, so
+// the load latency overlaps the LDS work instead of adding to it.
+static_assert(TILE_ROWS * 4 == NT, "one sixteen-byte chunk per thread");
+template <int D>
+__global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
+{
+    __shared__ LocalShared<D> sh;
+    const int tid = threadIdx.x;
+    const int ntiles = a.ntx * a.nty;
+    int t = blockIdx.x;
+    uint4 raw = t < ntiles ? fetch_chunk(a, t, tid) : make_uint4(0u, 0u, 0u, 0u);
+    for (; t < ntiles; t += gridDim.x) {
+        sh.u.h[tid] = (uint16_t)chunk_mask(raw);
+        if (t + (int)gridDim.x < ntiles) raw = fetch_chunk(a, t + (int)gridDim.x, tid);
+        __syncthreads();
+        local_tile<D>(a, ws, sh, t, tid);
+        __syncthreads();
     }
 }
 
@@ -828,13 +883,38 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
 // launchers
 // ---------------------------------------------------------------------------
 
+// Workgroups of `kernel` that the current device holds at once (occupancy x
+// compute units), cached per device and kernel: the grid of a persistent
+// kernel.
+template <typename K>
+static unsigned resident_blocks(K kernel, int threads)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, unsigned> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(dev, reinterpret_cast<const void*>(kernel));
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 1;
+    const unsigned n = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(cus > 0 ? cus : 1);
+    cache[key] = n;
+    return n;
+}
+
 template <int D>
 static hipError_t launch_all(const ImageArgs& a, const Workspace& ws, hipStream_t st,
                              KernelTimer* timer, bool local_only)
 {
     const unsigned ntiles = (unsigned)a.ntx * (unsigned)a.nty;
+    const unsigned lgrid = std::min(ntiles, resident_blocks(k_local<D>, NT));
     timer_begin(timer, KIND_LOCAL, st);
-    k_local<D><<<ntiles, NT, 0, st>>>(a, ws);
+    k_local<D><<<lgrid, NT, 0, st>>>(a, ws);
     timer_end(timer, KIND_LOCAL, st);
     if (local_only) {
         timer_begin(timer, KIND_FINAL, st);
