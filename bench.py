@@ -182,6 +182,118 @@ def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_byt
         fh.write("\n".join(lines) + "\n")
 
 
+def bench_batch(ccl, torch, dev, check=True, n=256, reps=5):
+    """256 uint8 images, sides log-uniform in [64, 2048], half Bernoulli and
+    half blobs at random density, 8-connectivity: one ccl_label_batch call
+    against 256 ccl_label calls on the same stream (both issued through
+    precomputed ctypes arguments)."""
+    import ctypes
+    from paper_1712_09789_amd import workloads as wl
+    specs = wl.batch_specs(n, seed=0)
+    imgs = [wl.make(k, H, W, seed=sd, **kw) for (H, W, k, kw, sd) in specs]
+    px = sum(im.size for im in imgs)
+    dimgs = [torch.from_numpy(im).to(dev) for im in imgs]
+    outs = [torch.empty(im.shape, dtype=torch.int32, device=dev) for im in imgs]
+    lib = ccl.lib()
+    st = torch.cuda.current_stream()
+    sh = int(st.cuda_stream)
+    descs = ccl.make_descs(dimgs, outs, 8)
+    singles = [(d.data_ptr(), d.shape[0], d.shape[1], d.shape[1], 8, o.data_ptr(), sh)
+               for d, o in zip(dimgs, outs)]
+
+    def batch():
+        assert lib.ccl_label_batch(descs, n, sh) == 0
+
+    def per_image():
+        for a in singles:
+            lib.ccl_label(*a)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    t_single = timed(per_image)
+    t_batch = timed(batch)
+    # the same batch prepared once and replayed from a captured graph
+    plan = ccl.Plan(dimgs, 8, outs=outs)
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(st)
+    with torch.cuda.stream(cs):
+        plan.run(stream=cs)
+    st.wait_stream(cs)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.run()
+    t_graph = timed(g.replay)
+    exact = None
+    if check:
+        import oracle
+        batch()
+        torch.cuda.synchronize()
+        exact = all(np.array_equal(outs[i].cpu().numpy(), oracle.oracle_label(imgs[i], 8))
+                    for i in range(0, n, 8))
+    return {"images": n, "Mpx": round(px / 1e6, 2),
+            "batch_ms": round(1e3 * t_batch, 3), "per_image_ms": round(1e3 * t_single, 3),
+            "batch_Gpx/s": round(px / t_batch / 1e9, 1),
+            "per_image_Gpx/s": round(px / t_single / 1e9, 1),
+            "graph_ms": round(1e3 * t_graph, 3),
+            "graph_Gpx/s": round(px / t_graph / 1e9, 1),
+            "speedup": round(t_single / t_batch, 3),
+            "speedup_graph": round(t_single / t_graph, 3),
+            "exact_sampled": exact}
+
+
+def bench_serving(torch, dev, n=2000, seed=0):
+    """Poisson stream of frames 640x480 / 1920x1080 / 3840x2160 (weights
+    .5/.35/.15), blobs with sigma 8 thresholded at the median, 8-connectivity,
+    frames resident on the device.  The saturation rate S is the throughput
+    with every frame arriving at once; the stream then runs at 0.5 S and 0.8 S."""
+    from paper_1712_09789_amd import workloads as wl
+    from paper_1712_09789_amd.serve import GpuExecutor, Request, Scheduler
+    pool = {}
+    for H, W, _ in wl.SERVING_MIX:
+        pool[(H, W)] = [torch.from_numpy(wl.blobs(H, W, 8, seed=7 * H + k)).to(dev)
+                        for k in range(3)]
+    sizes = wl.serving_frames(n, seed)
+    rng = np.random.default_rng(seed)
+
+    def trace(rate):
+        t, reqs = 0.0, []
+        for i, (H, W, s) in enumerate(sizes):
+            if rate:
+                t += rng.exponential(1.0 / rate)
+            reqs.append(Request(rid=i, image=pool[(H, W)][s % 3], connectivity=8,
+                                arrival=t, H=H, W=W))
+        return reqs
+
+    ex = GpuExecutor(streams=4)
+
+    def serve(rate):
+        sched = Scheduler(ex, slots=4, max_batch=64)
+        stats = sched.run(trace(rate))
+        torch.cuda.synchronize()
+        for r in sched.done:
+            ex.release(r.labels)
+        return stats
+
+    serve(0.0)  # warm-up: buffers and workspaces
+    sat = serve(0.0)
+    s_rate = sat.completed / sat.makespan_s
+    out = {"frames": n, "saturation_frames_per_s": round(s_rate, 1),
+           "saturation": sat.as_dict()}
+    for frac in (0.5, 0.8):
+        out[f"rate_{frac}S"] = serve(frac * s_rate).as_dict()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +454,12 @@ def main():
             torch.cuda.empty_cache()
         result["extra_8192_conn8"] = extra
         log(f"[bench] 8192^2: {extra}")
+
+    if not args.no_extra:
+        result["batch_256"] = bench_batch(ccl, torch, dev, check=cpu is not None)
+        log(f"[bench] batch: {result['batch_256']}")
+        result["serving"] = bench_serving(torch, dev)
+        log(f"[bench] serving: {result['serving']}")
 
     print(json.dumps(result), flush=True)
 

@@ -87,6 +87,25 @@ typedef struct {
 int ccl_label_batch(const ccl_image_desc* descs, int32_t n, void* stream);
 
 /*
+ * Prepared batches, for callers that launch the same batch repeatedly (new
+ * pixels written into the same buffers) or capture it into a HIP graph.
+ * ccl_plan_create validates the descriptors exactly like ccl_label_batch,
+ * allocates the plan's own device memory (hipMalloc), copies the image
+ * tables and fills the tile index on `stream`, and waits for that stream.
+ * The image and label pointers of every descriptor are bound to the plan.
+ * ccl_plan_run enqueues only kernel launches on `stream` — no allocation, no
+ * copy, no synchronisation — so it may be captured into a graph; outputs are
+ * identical to ccl_label_batch on the same descriptors.  Runs of one plan on
+ * different streams must not overlap (they share its workspace).
+ * ccl_plan_destroy synchronises the plan's device and frees it (NULL is a
+ * no-op).
+ */
+typedef struct ccl_plan ccl_plan;
+int ccl_plan_create(const ccl_image_desc* descs, int32_t n, void* stream, ccl_plan** plan);
+int ccl_plan_run(ccl_plan* plan, void* stream);
+int ccl_plan_destroy(ccl_plan* plan);
+
+/*
  * Debugging aid for the local step alone (Section 3.1): every tile is
  * labelled as if it were a separate image, and each foreground pixel gets
  * 1 + the raster position (in the whole image) of the smallest pixel of its

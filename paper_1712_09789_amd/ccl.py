@@ -60,6 +60,12 @@ def _load() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_int64), i32]
     lib.ccl_copy_bytes.restype = ctypes.c_int
     lib.ccl_copy_bytes.argtypes = [vp, vp, i64, vp]
+    lib.ccl_plan_create.restype = ctypes.c_int
+    lib.ccl_plan_create.argtypes = [ctypes.POINTER(ImageDesc), i32, vp, ctypes.POINTER(vp)]
+    lib.ccl_plan_run.restype = ctypes.c_int
+    lib.ccl_plan_run.argtypes = [vp, vp]
+    lib.ccl_plan_destroy.restype = ctypes.c_int
+    lib.ccl_plan_destroy.argtypes = [vp]
     return lib
 
 
@@ -188,3 +194,38 @@ def copy_bytes(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
         raise ValueError("dst is smaller than src")
     _check(_lib.ccl_copy_bytes(src.data_ptr(), dst.data_ptr(), nbytes,
                                _stream_handle(stream)))
+
+
+class Plan:
+    """A prepared batch (ccl_plan_*): the images and label buffers are bound
+    at creation; run() only launches kernels, so it can be captured into a
+    graph (torch.cuda.graph) and replayed after new pixels are written into
+    the same input tensors."""
+
+    def __init__(self, imgs: Sequence[torch.Tensor], connectivity=8,
+                 outs: Sequence[torch.Tensor] | None = None, stream=None):
+        if outs is None:
+            outs = [_out_for(im, None) for im in imgs]
+        else:
+            outs = [_out_for(im, o) for im, o in zip(imgs, outs)]
+        self.imgs, self.outs = list(imgs), list(outs)
+        self._descs = make_descs(self.imgs, self.outs, connectivity)
+        h = ctypes.c_void_p()
+        _check(_lib.ccl_plan_create(self._descs, len(self.imgs), _stream_handle(stream),
+                                    ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None) -> list:
+        _check(_lib.ccl_plan_run(self._h, _stream_handle(stream)))
+        return self.outs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.ccl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -172,7 +172,117 @@ static ImageArgs make_args(const uint8_t* img, int32_t H, int32_t W, int64_t pit
     a.vec_in = ((uintptr_t)img % 16 == 0) && (pitch % 16 == 0);
     a.vec_out = ((uintptr_t)labels % 16 == 0) && (W % 4 == 0);
     a.wmagic = W == 1 ? 0xffffffffu : (uint32_t)((1ull << 32) / (uint64_t)W);
+    a.tbase = 0;
     return a;
+}
+
+static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+// Sizes of one connectivity class of a batch.
+struct ClassLayout {
+    int n = 0;
+    std::vector<int64_t> toff, goff, soff;  // prefix offsets (n+1 each)
+    int64_t ntiles = 0, ngroups = 0, nseamwg = 0;
+    int64_t head = 0;  // bytes of the device tables (0 for a single image)
+    int64_t bytes() const { return head + workspace_bytes(ntiles); }
+};
+
+static int layout_class(std::vector<ImageArgs>& imgs, int conn, ClassLayout& L, const char* who)
+{
+    const int n = (int)imgs.size();
+    L.n = n;
+    L.toff.assign(n + 1, 0);
+    L.goff.assign(n + 1, 0);
+    L.soff.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        ImageArgs& a = imgs[i];
+        a.tbase = L.toff[i];
+        L.toff[i + 1] = L.toff[i] + (int64_t)a.ntx * a.nty;
+        L.goff[i + 1] = L.goff[i] + image_groups(a.ntx, a.nty);
+        const int64_t items = image_seam_items(a.ntx, a.nty, a.H, a.W, conn);
+        L.soff[i + 1] = L.soff[i] + (items + SEAM_WG - 1) / SEAM_WG;
+    }
+    L.ntiles = L.toff[n];
+    L.ngroups = L.goff[n];
+    L.nseamwg = L.soff[n];
+    if (L.ntiles * NSLOTS > (int64_t)INT32_MAX)
+        return fail(CCL_ERR_TOO_LARGE, "%s: %lld tiles exceed the node id range", who,
+                    (long long)L.ntiles);
+    L.head = 0;
+    if (n > 1)
+        L.head = align256(n * (int64_t)sizeof(ImageArgs)) + 3 * align256((n + 1) * 8) +
+                 align256(L.ntiles * 4) + align256(L.ngroups * 4) + align256(L.nseamwg * 4);
+    return CCL_OK;
+}
+
+// Point the batch arguments and the workspace at device memory `base`
+// (L.bytes() long) and enqueue the copy of the image tables.
+static int bind_class(const std::vector<ImageArgs>& imgs, const ClassLayout& L, void* base,
+                      bool local_only, hipStream_t st, BatchArgs& b, Workspace& ws,
+                      const char* who)
+{
+    const int n = L.n;
+    b = BatchArgs{};
+    b.n = n;
+    b.ntiles = L.ntiles;
+    b.ngroups = local_only ? 0 : L.ngroups;
+    b.nseamwg = local_only ? 0 : L.nseamwg;
+    char* d = static_cast<char*>(base);
+    if (n == 1) {
+        b.one = imgs[0];
+    } else {
+        const int64_t tables = align256(n * (int64_t)sizeof(ImageArgs)) + 3 * align256((n + 1) * 8);
+        std::vector<char> host((size_t)tables, 0);
+        char* h = host.data();
+        std::memcpy(h, imgs.data(), n * sizeof(ImageArgs));
+        b.imgs = reinterpret_cast<const ImageArgs*>(d);
+        int64_t o = align256(n * (int64_t)sizeof(ImageArgs));
+        const std::vector<int64_t>* tabs[3] = {&L.toff, &L.goff, &L.soff};
+        const int64_t* dtabs[3];
+        for (int k = 0; k < 3; ++k) {
+            std::memcpy(h + o, tabs[k]->data(), (n + 1) * 8);
+            dtabs[k] = reinterpret_cast<const int64_t*>(d + o);
+            o += align256((n + 1) * 8);
+        }
+        b.tile_off = dtabs[0];
+        b.group_off = dtabs[1];
+        b.seam_off = dtabs[2];
+        // pageable source: the copy has read it when the call returns
+        hipError_t e = hipMemcpyAsync(d, h, host.size(), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess)
+            return fail(CCL_ERR_HIP, "%s: table copy: %s", who, hipGetErrorString(e));
+        b.tile_img = reinterpret_cast<int32_t*>(d + o);
+        o += align256(L.ntiles * 4);
+        b.group_img = reinterpret_cast<int32_t*>(d + o);
+        o += align256(L.ngroups * 4);
+        b.seam_img = reinterpret_cast<int32_t*>(d + o);
+    }
+    ws = carve_workspace(d + L.head, L.ntiles);
+    return CCL_OK;
+}
+
+// Label images of one connectivity with one set of launches.  A single image
+// travels in the kernel arguments; several get a device table (copied into
+// the head of the workspace) that maps global tiles, merge groups and seam
+// workgroups back to their image.
+static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, bool local_only,
+                     const char* who)
+{
+    if (imgs.empty()) return CCL_OK;
+    ClassLayout L;
+    int rc = layout_class(imgs, conn, L, who);
+    if (rc != CCL_OK) return rc;
+    void* base = nullptr;
+    rc = get_workspace(L.bytes(), st, &base);
+    if (rc != CCL_OK) return rc;
+    BatchArgs b;
+    Workspace ws;
+    rc = bind_class(imgs, L, base, local_only, st, b, ws, who);
+    if (rc != CCL_OK) return rc;
+    hipError_t e = launch_index(b, st);
+    if (e == hipSuccess) e = launch_label(b, conn, ws, st, active_timer(), local_only);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return CCL_OK;
 }
 
 static int label_one(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, int32_t conn,
@@ -180,19 +290,25 @@ static int label_one(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, in
 {
     int rc = validate(img, H, W, pitch, conn, labels, who);
     if (rc != CCL_OK || H == 0 || W == 0) return rc;
-    ImageArgs a = make_args(img, H, W, pitch, conn, labels);
-    const int64_t ntiles = (int64_t)a.ntx * a.nty;
-    void* base = nullptr;
-    rc = get_workspace(workspace_bytes(ntiles), st, &base);
-    if (rc != CCL_OK) return rc;
-    hipError_t e = launch_label(a, carve_workspace(base, ntiles), st, active_timer(), local_only);
-    if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
-    return CCL_OK;
+    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch, conn, labels));
+    return run_batch(one, conn, st, local_only, who);
 }
 
 }  // namespace ccl
 
 using namespace ccl;
+
+// A prepared batch: own device memory, tables filled, ready to launch.
+struct ccl_plan {
+    int device = 0;
+    void* mem = nullptr;
+    struct Class {
+        int conn;
+        BatchArgs b;
+        Workspace ws;
+    };
+    std::vector<Class> classes;
+};
 
 extern "C" {
 
@@ -225,12 +341,120 @@ int ccl_label_batch(const ccl_image_desc* descs, int32_t n, void* stream)
         int rc = validate(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels, who);
         if (rc != CCL_OK) return rc;
     }
+    // the node ids of each connectivity class must fit in int32 (checked
+    // before anything is enqueued)
+    int64_t class_tiles[2] = {0, 0};
     for (int32_t i = 0; i < n; ++i) {
         const ccl_image_desc& d = descs[i];
-        int rc = label_one(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels,
-                           static_cast<hipStream_t>(stream), false, "ccl_label_batch");
+        class_tiles[d.connectivity == 8] +=
+            (int64_t)((d.W + TW - 1) / TW) * ((d.H + TILE_ROWS - 1) / TILE_ROWS);
+    }
+    for (int c = 0; c < 2; ++c)
+        if (class_tiles[c] * NSLOTS > (int64_t)INT32_MAX)
+            return fail(CCL_ERR_TOO_LARGE, "ccl_label_batch: %lld tiles of connectivity %d "
+                        "exceed the node id range", (long long)class_tiles[c], c ? 8 : 4);
+    // one set of launches per connectivity
+    std::vector<ImageArgs> by_conn[2];
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        if (d.H == 0 || d.W == 0) continue;
+        by_conn[d.connectivity == 8].push_back(
+            make_args(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels));
+    }
+    for (int c = 0; c < 2; ++c) {
+        int rc = run_batch(by_conn[c], c ? 8 : 4, static_cast<hipStream_t>(stream), false,
+                           "ccl_label_batch");
         if (rc != CCL_OK) return rc;
     }
+    return CCL_OK;
+}
+
+int ccl_plan_create(const ccl_image_desc* descs, int32_t n, void* stream, ccl_plan** plan)
+{
+    g_err.clear();
+    if (!plan) return fail(CCL_ERR_INVALID_ARG, "ccl_plan_create: null plan pointer");
+    *plan = nullptr;
+    if (n < 0 || (n > 0 && !descs)) return fail(CCL_ERR_INVALID_ARG, "ccl_plan_create: bad descriptors");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<ImageArgs> by_conn[2];
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        char who[64];
+        snprintf(who, sizeof who, "ccl_plan_create[%d]", i);
+        int rc = validate(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels, who);
+        if (rc != CCL_OK) return rc;
+        if (d.H == 0 || d.W == 0) continue;
+        by_conn[d.connectivity == 8].push_back(
+            make_args(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels));
+    }
+    ClassLayout L[2];
+    int64_t total = 0;
+    for (int c = 0; c < 2; ++c) {
+        if (by_conn[c].empty()) continue;
+        int rc = layout_class(by_conn[c], c ? 8 : 4, L[c], "ccl_plan_create");
+        if (rc != CCL_OK) return rc;
+        total += align256(L[c].bytes());
+    }
+    ccl_plan* p = new ccl_plan;
+    (void)hipGetDevice(&p->device);
+    if (total > 0) {
+        hipError_t e = hipMalloc(&p->mem, (size_t)total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete p;
+            return fail(CCL_ERR_OUT_OF_MEMORY, "ccl_plan_create: %lld bytes: %s",
+                        (long long)total, hipGetErrorString(e));
+        }
+    }
+    char* base = static_cast<char*>(p->mem);
+    for (int c = 0; c < 2; ++c) {
+        if (by_conn[c].empty()) continue;
+        ccl_plan::Class k;
+        k.conn = c ? 8 : 4;
+        int rc = bind_class(by_conn[c], L[c], base, false, st, k.b, k.ws, "ccl_plan_create");
+        hipError_t e = rc == CCL_OK ? launch_index(k.b, st) : hipSuccess;
+        if (rc != CCL_OK || e != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(p->mem);
+            delete p;
+            return rc != CCL_OK ? rc : fail(CCL_ERR_HIP, "ccl_plan_create: %s", hipGetErrorString(e));
+        }
+        p->classes.push_back(k);
+        base += align256(L[c].bytes());
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(p->mem);
+        delete p;
+        return fail(CCL_ERR_HIP, "ccl_plan_create: %s", hipGetErrorString(e));
+    }
+    *plan = p;
+    return CCL_OK;
+}
+
+int ccl_plan_run(ccl_plan* plan, void* stream)
+{
+    g_err.clear();
+    if (!plan) return fail(CCL_ERR_INVALID_ARG, "ccl_plan_run: null plan");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (auto& k : plan->classes) {
+        hipError_t e = launch_label(k.b, k.conn, k.ws, st, active_timer(), false);
+        if (e != hipSuccess) return fail(CCL_ERR_HIP, "ccl_plan_run: %s", hipGetErrorString(e));
+    }
+    return CCL_OK;
+}
+
+int ccl_plan_destroy(ccl_plan* plan)
+{
+    g_err.clear();
+    if (!plan) return CCL_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(plan->device);
+    (void)hipDeviceSynchronize();
+    if (plan->mem) (void)hipFree(plan->mem);
+    (void)hipSetDevice(prev);
+    delete plan;
     return CCL_OK;
 }
 

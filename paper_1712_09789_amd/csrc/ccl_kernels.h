@@ -27,6 +27,24 @@ struct ImageArgs {
     int32_t vec_in;    // img and pitch are 16-byte aligned
     int32_t vec_out;   // labels rows are 16-byte aligned (W % 4 == 0)
     uint32_t wmagic;   // floor(2^32 / W) (0xffffffff for W = 1), for division by W
+    int64_t tbase;     // global index of the image's first tile in the workspace
+};
+
+// Images labelled by one set of launches (all of one connectivity).  With n
+// == 1 the image travels in `one` and the tables are unused; otherwise the
+// device tables map global tiles, merge groups and k_seam workgroups to
+// their image.
+struct BatchArgs {
+    ImageArgs one;
+    const ImageArgs* imgs;  // [n]
+    const int64_t* tile_off;   // [n+1] first global tile of each image (= tbase)
+    const int64_t* group_off;  // [n+1] first global merge group of each image
+    const int64_t* seam_off;   // [n+1] first k_seam workgroup of each image
+    int32_t* tile_img;   // [ntiles]  filled by k_index
+    int32_t* group_img;  // [ngroups]
+    int32_t* seam_img;   // [nseamwg]
+    int32_t n;
+    int64_t ntiles, ngroups, nseamwg;
 };
 
 // Device workspace of one image.
@@ -65,7 +83,15 @@ struct KernelTimer;  // host-side event recorder, null when timing is off
 void timer_begin(KernelTimer* t, int kind, hipStream_t st);
 void timer_end(KernelTimer* t, int kind, hipStream_t st);
 
-hipError_t launch_label(const ImageArgs& a, const Workspace& ws, hipStream_t st,
+// Tile-grid quantities of one image, shared by the host and the launchers.
+int64_t image_groups(int ntx, int nty);      // merge groups
+int64_t image_seam_items(int ntx, int nty, int H, int W, int conn);  // k_seam work items
+constexpr int SEAM_WG = 256;                 // k_seam workgroup size
+
+// k_index: fills the image-of-tile/group/seam-workgroup tables of a batch
+// (n > 1); must precede launch_label on the same stream.
+hipError_t launch_index(const BatchArgs& b, hipStream_t st);
+hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
                         KernelTimer* timer, bool local_only);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,
                        KernelTimer* timer);

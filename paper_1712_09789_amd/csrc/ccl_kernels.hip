@@ -293,6 +293,45 @@ constexpr uint32_t REP_TAG = 0x80000000u;
 // k_local
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// images of a batch
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ ImageArgs batch_image(const BatchArgs& b, int i)
+{
+    return b.n == 1 ? b.one : b.imgs[i];
+}
+__device__ __forceinline__ int tile_image(const BatchArgs& b, int64_t T)
+{
+    return b.n == 1 ? 0 : b.tile_img[T];
+}
+
+// Largest i with off[i] <= x, for off[0] = 0 <= x < off[n].
+__device__ int upper_index(const int64_t* off, int n, int64_t x)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Image of every global tile, merge group and k_seam workgroup of a batch.
+__global__ __launch_bounds__(256) void k_index(BatchArgs b)
+{
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < b.ntiles) {
+        b.tile_img[x] = upper_index(b.tile_off, b.n, x);
+    } else if (x < b.ntiles + b.ngroups) {
+        b.group_img[x - b.ntiles] = upper_index(b.group_off, b.n, x - b.ntiles);
+    } else if (x < b.ntiles + b.ngroups + b.nseamwg) {
+        const int64_t w = x - b.ntiles - b.ngroups;
+        b.seam_img[w] = upper_index(b.seam_off, b.n, w);
+    }
+}
+
 // Initialisation (Section 3.1.1): sixteen bytes of a tile, four threads per
 // row.  Bytes past the image edge read as background.  The raw bytes are
 // returned so that the load of the next tile can be in flight while the
@@ -331,10 +370,11 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
+    const int64_t T = a.tbase + t;  // global tile index (workspace)
     if (tid < TILE_ROWS) {
         const uint64_t m = sh.u.w[tid];
         sh.M[tid] = m;
-        ws.bits[(int64_t)t * TILE_ROWS + tid] = m;
+        ws.bits[T * TILE_ROWS + tid] = m;
     }
     __syncthreads();
     build_lines<D>(sh, tid);
@@ -484,7 +524,7 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
 
     // ID conversion (Section 3.1.4): the representative's forest node carries
     // the raster position of the component's smallest pixel.
-    const int64_t sbase = (int64_t)t * NSLOTS;
+    const int64_t sbase = T * NSLOTS;
     {
         int32_t node = -1;
         if (fg) {
@@ -501,7 +541,7 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
 
     // Run table: interior components store their root's tile key; border
     // components store their representative slot (and mark the root run).
-    uint16_t* rt = ws.runtab + (int64_t)t * RUNTAB_PER_TILE;
+    uint16_t* rt = ws.runtab + T * RUNTAB_PER_TILE;
     for (uint32_t id = tid; id < R; id += NT) {
         const uint32_t v = lds_ld(sh.P + id);
         uint16_t ent;
@@ -521,19 +561,30 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
 // the load latency overlaps the LDS work instead of adding to it.
 static_assert(TILE_ROWS * 4 == NT, "one sixteen-byte chunk per thread");
 template <int D>
-__global__ __launch_bounds__(NT) void k_local(ImageArgs a, Workspace ws)
+__global__ __launch_bounds__(NT) void k_local(BatchArgs b, Workspace ws)
 {
     __shared__ LocalShared<D> sh;
     const int tid = threadIdx.x;
-    const int ntiles = a.ntx * a.nty;
-    int t = blockIdx.x;
-    uint4 raw = t < ntiles ? fetch_chunk(a, t, tid) : make_uint4(0u, 0u, 0u, 0u);
-    for (; t < ntiles; t += gridDim.x) {
+    int64_t T = blockIdx.x;
+    if (T >= b.ntiles) return;
+    ImageArgs a = batch_image(b, tile_image(b, T));
+    int t = (int)(T - a.tbase);
+    uint4 raw = fetch_chunk(a, t, tid);
+    for (; T < b.ntiles; T += gridDim.x) {
         sh.u.h[tid] = (uint16_t)chunk_mask(raw);
-        if (t + (int)gridDim.x < ntiles) raw = fetch_chunk(a, t + (int)gridDim.x, tid);
+        const int64_t TN = T + gridDim.x;
+        ImageArgs an = a;
+        int tn = 0;
+        if (TN < b.ntiles) {
+            an = batch_image(b, tile_image(b, TN));
+            tn = (int)(TN - an.tbase);
+            raw = fetch_chunk(an, tn, tid);
+        }
         __syncthreads();
         local_tile<D>(a, ws, sh, t, tid);
         __syncthreads();
+        a = an;
+        t = tn;
     }
 }
 
@@ -609,7 +660,7 @@ struct SeamNodes {
 __device__ __forceinline__ SeamNodes hseam_nodes(const ImageArgs& a, const int32_t* slots, int k,
                                                  int x)
 {
-    const int64_t top = (int64_t)(k - 1) * a.ntx, bot = (int64_t)k * a.ntx;
+    const int64_t top = a.tbase + (int64_t)(k - 1) * a.ntx, bot = a.tbase + (int64_t)k * a.ntx;
     SeamNodes n;
     n.ac = slots[(top + x / TW) * NSLOTS + TW + x % TW];
     n.bc = slots[(bot + x / TW) * NSLOTS + x % TW];
@@ -626,8 +677,9 @@ __device__ __forceinline__ SeamNodes vseam_nodes(const ImageArgs& a, const int32
                                                  int y)
 {
     const int k = y / TILE_ROWS, yl = y - k * TILE_ROWS;
-    const int32_t* left = slots + ((int64_t)k * a.ntx + j - 1) * NSLOTS + 2 * TW + TILE_ROWS;
-    const int32_t* right = slots + ((int64_t)k * a.ntx + j) * NSLOTS + 2 * TW;
+    const int32_t* left =
+        slots + (a.tbase + (int64_t)k * a.ntx + j - 1) * NSLOTS + 2 * TW + TILE_ROWS;
+    const int32_t* right = slots + (a.tbase + (int64_t)k * a.ntx + j) * NSLOTS + 2 * TW;
     SeamNodes n;
     n.ac = left[yl];
     n.bc = right[yl];
@@ -636,88 +688,125 @@ __device__ __forceinline__ SeamNodes vseam_nodes(const ImageArgs& a, const int32
     return n;
 }
 
-// Group-local index of a node: (tile within group) * NSLOTS + slot.  The
-// tile is given by its image tile coordinates.
-__device__ __forceinline__ uint32_t group_idx(int32_t node, int tx, int ty, int tx0, int ty0,
-                                              int ntx)
-{
-    const int32_t slot = node - (int32_t)(((int64_t)ty * ntx + tx) * NSLOTS);
-    return (uint32_t)(((ty - ty0) * BX + (tx - tx0)) * NSLOTS + slot);
-}
-
 constexpr int NTB = 1024;  // threads per merge-group workgroup
 
 template <int D>
-__global__ __launch_bounds__(NTB) void k_block(ImageArgs a, Workspace ws)
+__global__ __launch_bounds__(NTB) void k_block(BatchArgs b, Workspace ws)
 {
-    __shared__ uint32_t P[BN];         // (group key << 16) | group index
+    __shared__ uint32_t P[BN];           // (group key << 16) | group index
+    __shared__ int32_t S[BN];            // the group's slot tables (node ids, -1 = bg)
     __shared__ uint32_t isrep[BN / 32];  // group indices that are forest nodes
     const int tid = threadIdx.x;
+    const int img = b.n == 1 ? 0 : b.group_img[blockIdx.x];
+    const ImageArgs a = batch_image(b, img);
+    const int g = (int)(blockIdx.x - (b.n == 1 ? 0 : b.group_off[img]));
     const int nbx = (a.ntx + BX - 1) / BX;
-    const int tx0 = (blockIdx.x % nbx) * BX, ty0 = (blockIdx.x / nbx) * BY;
+    const int tx0 = (g % nbx) * BX, ty0 = (g / nbx) * BY;
     const int px0 = tx0 * TW, py0 = ty0 * TILE_ROWS;
 
     for (int i = tid; i < BN / 32; i += NTB) isrep[i] = 0u;
     __syncthreads();
-    // nodes of the group, keyed by the position of their smallest pixel
-    // relative to the group origin (same order as raster position)
+    // One pass over the group's slot tables and forest entries (independent
+    // loads); nodes are keyed by the position of their smallest pixel
+    // relative to the group origin (same order as raster position).
     for (int li = tid; li < BN; li += NTB) {
         const int ti = li / NSLOTS, sl = li % NSLOTS;
         const int tx = tx0 + ti % BX, ty = ty0 + ti / BX;
-        if (tx >= a.ntx || ty >= a.nty) continue;
-        const int64_t node = ((int64_t)ty * a.ntx + tx) * NSLOTS + sl;
-        if (ws.slots[node] != (int32_t)node) continue;
-        uint32_t gy, gx;
-        divmod_w((uint32_t)(ws.forest[node] >> 32), (uint32_t)a.W, a.wmagic, gy, gx);
-        P[li] = pk((gy - py0) * BPX + (gx - px0), li);
-        atomicOr(isrep + (li >> 5), 1u << (li & 31));
+        int32_t node = -1;
+        if (tx < a.ntx && ty < a.nty) {
+            const int64_t base = (a.tbase + (int64_t)ty * a.ntx + tx) * NSLOTS;
+            node = ws.slots[base + sl];
+            const uint64_t f = ws.forest[base + sl];
+            if (node == (int32_t)(base + sl)) {
+                uint32_t gy, gx;
+                divmod_w((uint32_t)(f >> 32), (uint32_t)a.W, a.wmagic, gy, gx);
+                P[li] = pk((gy - py0) * BPX + (gx - px0), li);
+                atomicOr(isrep + (li >> 5), 1u << (li & 31));
+            }
+        }
+        S[li] = node;
     }
     __syncthreads();
 
+    // Node id -> group index, for a node of the group tile (txl, tyl).
+    auto gidx = [&](int32_t node, int txl, int tyl) {
+        const int ti = tyl * BX + txl;
+        const int64_t base = (a.tbase + (int64_t)(ty0 + tyl) * a.ntx + tx0 + txl) * NSLOTS;
+        return (uint32_t)(ti * NSLOTS + (int)(node - base));
+    };
     // seams between tile columns inside the group
     for (int it = tid; it < (BX - 1) * BPY; it += NTB) {
-        const int j = it / BPY + 1, y = py0 + it % BPY;
-        const int txr = tx0 + j;
-        if (txr >= a.ntx || y >= a.H) continue;
-        const int ty = y / TILE_ROWS;
-        const SeamNodes n = vseam_nodes(a, ws.slots, txr, y);
-        const int m = seam_edges<D>(n.ap, n.ac, n.bp, n.bc);
-        if (!m) continue;
-        auto L = [&](int32_t node) { return group_idx(node, txr - 1, ty, tx0, ty0, a.ntx); };
-        auto R = [&](int32_t node) { return group_idx(node, txr, ty, tx0, ty0, a.ntx); };
-        if (m & E_II) punion(P, L(n.ac), R(n.bc));
-        if (m & E_PI) punion(P, L(n.ap), R(n.bc));
-        if (m & E_IP) punion(P, L(n.ac), R(n.bp));
+        const int j = it / BPY + 1, yy = it % BPY;
+        if (tx0 + j >= a.ntx || py0 + yy >= a.H) continue;
+        const int tyl = yy / TILE_ROWS, yl = yy % TILE_ROWS;
+        const int32_t* L = S + (tyl * BX + j - 1) * NSLOTS + 2 * TW + TILE_ROWS;
+        const int32_t* Rr = S + (tyl * BX + j) * NSLOTS + 2 * TW;
+        const int32_t ac = L[yl], bc = Rr[yl];
+        const int32_t ap = yl > 0 ? L[yl - 1] : -1, bp = yl > 0 ? Rr[yl - 1] : -1;
+        const int m = seam_edges<D>(ap, ac, bp, bc);
+        if (m & E_II) punion(P, gidx(ac, j - 1, tyl), gidx(bc, j, tyl));
+        if (m & E_PI) punion(P, gidx(ap, j - 1, tyl), gidx(bc, j, tyl));
+        if (m & E_IP) punion(P, gidx(ac, j - 1, tyl), gidx(bp, j, tyl));
     }
     // seams between tile rows inside the group; diagonal edges that reach the
     // group to the left belong to k_seam
     for (int it = tid; it < (BY - 1) * BPX; it += NTB) {
-        const int k = ty0 + it / BPX + 1, x = px0 + it % BPX;
-        if (k >= a.nty || x >= a.W) continue;
-        const SeamNodes n = hseam_nodes(a, ws.slots, k, x);
-        int m = seam_edges<D>(n.ap, n.ac, n.bp, n.bc);
-        if (x == px0) m &= E_II;
-        if (!m) continue;
-        const int tx = x / TW, txp = (x - 1) / TW;
-        auto T0 = [&](int32_t node, int txx) { return group_idx(node, txx, k - 1, tx0, ty0, a.ntx); };
-        auto B0 = [&](int32_t node, int txx) { return group_idx(node, txx, k, tx0, ty0, a.ntx); };
-        if (m & E_II) punion(P, T0(n.ac, tx), B0(n.bc, tx));
-        if (m & E_PI) punion(P, T0(n.ap, txp), B0(n.bc, tx));
-        if (m & E_IP) punion(P, T0(n.ac, tx), B0(n.bp, txp));
+        const int k = it / BPX + 1, xx = it % BPX;
+        if (ty0 + k >= a.nty || px0 + xx >= a.W) continue;
+        const int txl = xx / TW, xl = xx % TW;
+        const int32_t* A = S + ((k - 1) * BX + txl) * NSLOTS + TW;  // bottom row of the upper tile
+        const int32_t* B = S + (k * BX + txl) * NSLOTS;             // top row of the lower tile
+        const int32_t ac = A[xl], bc = B[xl];
+        int32_t ap = -1, bp = -1;
+        int txp = txl;
+        if (xx > 0) {
+            txp = (xx - 1) / TW;
+            const int xp = (xx - 1) % TW;
+            ap = S[((k - 1) * BX + txp) * NSLOTS + TW + xp];
+            bp = S[(k * BX + txp) * NSLOTS + xp];
+        }
+        const int m = seam_edges<D>(ap, ac, bp, bc);
+        if (m & E_II) punion(P, gidx(ac, txl, k - 1), gidx(bc, txl, k));
+        if (m & E_PI) punion(P, gidx(ap, txp, k - 1), gidx(bc, txl, k));
+        if (m & E_IP) punion(P, gidx(ac, txl, k - 1), gidx(bp, txp, k));
     }
     __syncthreads();
 
-    // every node of the group now points at its group root
+    // Every node of the group now points at its group root in the forest, and
+    // the border slots that k_seam reads (the group's outer rows and columns,
+    // and the end pixels of tile rows at the group's left and right columns)
+    // name that group root directly.
     for (int li = tid; li < BN; li += NTB) {
-        if (!((isrep[li >> 5] >> (li & 31)) & 1u)) continue;
-        const uint32_t r = pfind(P, (uint32_t)li);
-        const uint32_t rl = pk_id(r), rk = pk_key(r);
+        const int ti = li / NSLOTS, sl = li % NSLOTS;
+        const int txl = ti % BX, tyl = ti / BX;
+        const int tx = tx0 + txl, ty = ty0 + tyl;
+        if (tx >= a.ntx || ty >= a.nty) continue;
+        const int64_t base = (a.tbase + (int64_t)ty * a.ntx + tx) * NSLOTS;
         auto node_of = [&](uint32_t l) {
-            const int ti = (int)(l / NSLOTS), sl = (int)(l % NSLOTS);
-            return (uint32_t)(((int64_t)(ty0 + ti / BX) * a.ntx + tx0 + ti % BX) * NSLOTS + sl);
+            const int tj = (int)(l / NSLOTS);
+            return (uint32_t)((a.tbase + (int64_t)(ty0 + tj / BX) * a.ntx + tx0 + tj % BX) *
+                                  NSLOTS +
+                              (int)(l % NSLOTS));
         };
-        const uint32_t gkey = (uint32_t)((int64_t)(py0 + (int)(rk / BPX)) * a.W + px0 + (int)(rk % BPX));
-        ws.forest[node_of((uint32_t)li)] = ((uint64_t)gkey << 32) | node_of(rl);
+        if ((isrep[li >> 5] >> (li & 31)) & 1u) {
+            const uint32_t r = pfind(P, (uint32_t)li);
+            const uint32_t rk = pk_key(r);
+            const uint32_t gkey =
+                (uint32_t)((int64_t)(py0 + (int)(rk / BPX)) * a.W + px0 + (int)(rk % BPX));
+            ws.forest[base + sl] = ((uint64_t)gkey << 32) | node_of(pk_id(r));
+        }
+        const int32_t node = S[li];
+        if (node < 0) continue;
+        const bool top = sl < TW, bot = sl >= TW && sl < 2 * TW;
+        const int xs = sl % TW;
+        const bool outer = (top && tyl == 0) || (bot && tyl == BY - 1) ||
+                           (sl >= 2 * TW && sl < 2 * TW + TILE_ROWS && txl == 0) ||
+                           (sl >= 2 * TW + TILE_ROWS && txl == BX - 1) ||
+                           ((top || bot) && ((xs == 0 && txl == 0) || (xs == TW - 1 && txl == BX - 1)));
+        if (outer) {
+            const uint32_t r = pfind(P, gidx(node, txl, tyl));
+            ws.slots[base + sl] = (int32_t)node_of(pk_id(r));
+        }
     }
 }
 
@@ -726,9 +815,12 @@ __global__ __launch_bounds__(NTB) void k_block(ImageArgs a, Workspace ws)
 // group columns, and (8-connectivity) the two diagonal edges that cross a
 // group column at each seam between tile rows inside a group.
 template <int D>
-__global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
+__global__ __launch_bounds__(SEAM_WG) void k_seam(BatchArgs b, Workspace ws)
 {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int img = b.n == 1 ? 0 : b.seam_img[blockIdx.x];
+    const ImageArgs a = batch_image(b, img);
+    const int64_t wg = blockIdx.x - (b.n == 1 ? 0 : b.seam_off[img]);
+    const int64_t gid = wg * SEAM_WG + threadIdx.x;
     const int nkh = (a.nty - 1) / BY, nkv = (a.ntx - 1) / BX;
     const int nbx = (a.ntx + BX - 1) / BX;
     const int64_t nh = (int64_t)nkh * a.W, nv = (int64_t)nkv * a.H;
@@ -753,15 +845,14 @@ __global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
         m = 0;
         n.ap = n.ac = n.bp = n.bc = -1;
     }
-    // Replace each node by its current parent (after k_block: its group root),
-    // then drop pairs another item of this workgroup already holds: along a
-    // seam most foreground stretches join the same two group roots, and one
-    // union per distinct pair is enough.  A full table only costs duplicates.
+    // The slots read here name group roots (k_block rewrote them); drop pairs
+    // another item of this workgroup already holds: along a seam most
+    // foreground stretches join the same two group roots, and one union per
+    // distinct pair is enough.  A full table only costs duplicates.
     __shared__ unsigned long long seen[SEAM_HASH];
     for (int i = threadIdx.x; i < SEAM_HASH; i += blockDim.x) seen[i] = ~0ull;
     __syncthreads();
     uint64_t* F = ws.forest;
-    auto parent = [&](int32_t node) { return (uint32_t)g_ld(F + node); };
     auto unite = [&](uint32_t x, uint32_t y) {
         if (x == y) return;
         if (x > y) { uint32_t t = x; x = y; y = t; }
@@ -774,9 +865,9 @@ __global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
         }
         g_union(F, x, y);
     };
-    if (m & E_II) unite(parent(n.ac), parent(n.bc));
-    if (m & E_PI) unite(parent(n.ap), parent(n.bc));
-    if (m & E_IP) unite(parent(n.ac), parent(n.bp));
+    if (m & E_II) unite((uint32_t)n.ac, (uint32_t)n.bc);
+    if (m & E_PI) unite((uint32_t)n.ap, (uint32_t)n.bc);
+    if (m & E_IP) unite((uint32_t)n.ac, (uint32_t)n.bp);
 }
 
 // ---------------------------------------------------------------------------
@@ -785,39 +876,43 @@ __global__ __launch_bounds__(256) void k_seam(ImageArgs a, Workspace ws)
 
 template <int D>
 struct FinalShared : Lines<D> {
-    int32_t lab[Geo<D>::MAXR];  // final label of each run
-    int32_t fin[NSLOTS];        // final label of each border component, by slot
+    int32_t lab[Geo<D>::MAXR];             // final label of each run
+    int32_t fin[NSLOTS];                   // final label of each border component, by slot
+    alignas(16) uint16_t ent[RUNTAB_PER_TILE];  // the tile's run table
 };
+static_assert(RUNTAB_PER_TILE == 8 * NT, "one 16-byte run-table load per thread");
 
 // Update of the global label map (Section 3.3).  Each border component takes
 // 1 + the key of its global root, every other component 1 + the raster
 // position of its local root; each label is written once.  With LOCAL_ONLY
 // the forest is read before any merge (every tile labelled as an image).
 template <int D, bool LOCAL_ONLY>
-__global__ __launch_bounds__(NT) void k_final(ImageArgs a, Workspace ws)
+__global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws)
 {
     __shared__ FinalShared<D> sh;
     const int tid = threadIdx.x;
-    const int t = blockIdx.x;
+    const int64_t T = blockIdx.x;  // global tile
+    const ImageArgs a = batch_image(b, tile_image(b, T));
+    const int t = (int)(T - a.tbase);
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
-    if (tid < TILE_ROWS) sh.M[tid] = ws.bits[(int64_t)t * TILE_ROWS + tid];
+    if (tid < TILE_ROWS) sh.M[tid] = ws.bits[T * TILE_ROWS + tid];
     __syncthreads();
     build_lines<D>(sh, tid);
     const uint32_t R = sh.base[Geo<D>::NL];
-    const uint16_t* rt = ws.runtab + (int64_t)t * RUNTAB_PER_TILE;
-    const int64_t sbase = (int64_t)t * NSLOTS;
+    const uint16_t* rt = ws.runtab + T * RUNTAB_PER_TILE;
+    const int64_t sbase = T * NSLOTS;
 
+    // the run table in one coalesced load (eight entries per thread)
+    if (8u * tid < R)
+        reinterpret_cast<uint4*>(sh.ent)[tid] = reinterpret_cast<const uint4*>(rt)[tid];
+    __syncthreads();
     // global root of each border component, looked up once (by its root run)
-    constexpr int PER = (Geo<D>::MAXR + NT - 1) / NT;  // run-table entries per thread
-    uint16_t ent[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const uint32_t id = tid + k * NT;
-        ent[k] = id < R ? rt[id] : (uint16_t)0;
-        if (id < R && (ent[k] & (RT_BORDER | RT_ROOT)) == (RT_BORDER | RT_ROOT)) {
-            const int rep = ent[k] & 0x3fff;
+    for (uint32_t id = tid; id < R; id += NT) {
+        const uint16_t e = sh.ent[id];
+        if ((e & (RT_BORDER | RT_ROOT)) == (RT_BORDER | RT_ROOT)) {
+            const int rep = e & 0x3fff;
             const uint32_t key = LOCAL_ONLY
                                      ? (uint32_t)(g_ld(ws.forest + sbase + rep) >> 32)
                                      : g_find_ro(ws.forest, (uint32_t)(sbase + rep)).key;
@@ -825,17 +920,13 @@ __global__ __launch_bounds__(NT) void k_final(ImageArgs a, Workspace ws)
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const uint32_t id = tid + k * NT;
-        if (id < R) {
-            const uint16_t e = ent[k];
-            // border component: its global root; otherwise ID conversion of
-            // the interior component's local root
-            sh.lab[id] = (e & RT_BORDER)
-                             ? sh.fin[e & 0x3fff]
-                             : (int32_t)((int64_t)(gy0 + e / TW) * a.W + gx0 + e % TW + 1);
-        }
+    for (uint32_t id = tid; id < R; id += NT) {
+        const uint32_t e = sh.ent[id];
+        // border component: its global root; otherwise ID conversion of the
+        // interior component's local root
+        sh.lab[id] = (e & RT_BORDER)
+                         ? sh.fin[e & 0x3fff]
+                         : (int32_t)((int64_t)(gy0 + (int)(e / TW)) * a.W + gx0 + (int)(e % TW) + 1);
     }
     __syncthreads();
 
@@ -907,45 +998,65 @@ static unsigned resident_blocks(K kernel, int threads)
     return n;
 }
 
+int64_t image_groups(int ntx, int nty)
+{
+    return (int64_t)((ntx + BX - 1) / BX) * ((nty + BY - 1) / BY);
+}
+
+int64_t image_seam_items(int ntx, int nty, int H, int W, int conn)
+{
+    const int nbx = (ntx + BX - 1) / BX;
+    const int nkh = (nty - 1) / BY, nkv = (ntx - 1) / BX;
+    return (int64_t)nkh * W + (int64_t)nkv * H +
+           (conn == 8 ? (int64_t)(nty - 1 - nkh) * (nbx - 1) : 0);
+}
+
 template <int D>
-static hipError_t launch_all(const ImageArgs& a, const Workspace& ws, hipStream_t st,
+static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_t st,
                              KernelTimer* timer, bool local_only)
 {
-    const unsigned ntiles = (unsigned)a.ntx * (unsigned)a.nty;
-    const unsigned lgrid = std::min(ntiles, resident_blocks(k_local<D>, NT));
+    if (b.ntiles <= 0) return hipSuccess;
+    const unsigned lgrid =
+        (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_local<D>, NT));
     timer_begin(timer, KIND_LOCAL, st);
-    k_local<D><<<lgrid, NT, 0, st>>>(a, ws);
+    k_local<D><<<lgrid, NT, 0, st>>>(b, ws);
     timer_end(timer, KIND_LOCAL, st);
     if (local_only) {
         timer_begin(timer, KIND_FINAL, st);
-        k_final<D, true><<<ntiles, NT, 0, st>>>(a, ws);
+        k_final<D, true><<<(unsigned)b.ntiles, NT, 0, st>>>(b, ws);
         timer_end(timer, KIND_FINAL, st);
         return hipGetLastError();
     }
-    const int nbx = (a.ntx + BX - 1) / BX, nby = (a.nty + BY - 1) / BY;
-    if (a.ntx > 1 || a.nty > 1) {
+    // a single-tile image has no seams
+    if (b.ngroups > 0) {
         timer_begin(timer, KIND_BLOCK, st);
-        k_block<D><<<(unsigned)(nbx * nby), NTB, 0, st>>>(a, ws);
+        k_block<D><<<(unsigned)b.ngroups, NTB, 0, st>>>(b, ws);
         timer_end(timer, KIND_BLOCK, st);
     }
-    const int64_t items = (int64_t)((a.nty - 1) / BY) * a.W + (int64_t)((a.ntx - 1) / BX) * a.H +
-                          (D ? (int64_t)(a.nty - 1 - (a.nty - 1) / BY) * (nbx - 1) : 0);
-    if (items > 0) {
+    if (b.nseamwg > 0) {
         timer_begin(timer, KIND_SEAM, st);
-        k_seam<D><<<(unsigned)((items + 255) / 256), 256, 0, st>>>(a, ws);
+        k_seam<D><<<(unsigned)b.nseamwg, SEAM_WG, 0, st>>>(b, ws);
         timer_end(timer, KIND_SEAM, st);
     }
     timer_begin(timer, KIND_FINAL, st);
-    k_final<D, false><<<ntiles, NT, 0, st>>>(a, ws);
+    k_final<D, false><<<(unsigned)b.ntiles, NT, 0, st>>>(b, ws);
     timer_end(timer, KIND_FINAL, st);
     return hipGetLastError();
 }
 
-hipError_t launch_label(const ImageArgs& a, const Workspace& ws, hipStream_t st,
+hipError_t launch_index(const BatchArgs& b, hipStream_t st)
+{
+    if (b.n <= 1) return hipSuccess;
+    const int64_t idx = b.ntiles + b.ngroups + b.nseamwg;
+    if (idx > 0) k_index<<<(unsigned)((idx + 255) / 256), 256, 0, st>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
                         KernelTimer* timer, bool local_only)
 {
-    if (a.conn == 8) return launch_all<1>(a, ws, st, timer, local_only);
-    return launch_all<0>(a, ws, st, timer, local_only);
+    if (conn == 8) return launch_all<1>(b, ws, st, timer, local_only);
+    return launch_all<0>(b, ws, st, timer, local_only);
 }
 
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,

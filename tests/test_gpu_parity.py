@@ -221,3 +221,73 @@ def test_batch_matches_single(ccl):
     torch.cuda.synchronize()
     for im, c, o in zip(imgs, conns, outs):
         assert np.array_equal(o.cpu().numpy(), oracle_label(im, c))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batch_uneven_mixed(ccl, seed):
+    """Uneven batch (tiny, ragged, empty, single-tile and multi-group images,
+    both connectivities): every image equals the oracle, and equals itself
+    labelled alone; a shuffled order gives the same outputs."""
+    rng = np.random.default_rng(seed)
+    specs = wl.batch_specs(40, seed=seed, lo=1, hi=600)
+    imgs = [wl.make(k, H, W, seed=s, **kw) for (H, W, k, kw, s) in specs]
+    imgs += [np.zeros((0, 5), np.uint8), wl.full(1, 1), wl.checkerboard(64, 64),
+             wl.bernoulli(300, 700, 0.55, seed=9)]
+    conns = [int(c) for c in rng.choice([4, 8], size=len(imgs))]
+    devs = [to_dev(im) for im in imgs]
+    outs = ccl.label_batch(devs, conns)
+    torch.cuda.synchronize()
+    for im, c, o in zip(imgs, conns, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle_label(im, c))
+    order = rng.permutation(len(imgs))
+    outs2 = ccl.label_batch([devs[i] for i in order], [conns[i] for i in order])
+    torch.cuda.synchronize()
+    for j, i in enumerate(order):
+        assert np.array_equal(outs2[j].cpu().numpy(), outs[i].cpu().numpy())
+
+
+def test_batch_c4_shapes(ccl):
+    """The batched workload's shape mix (256 images, sides log-uniform in
+    [64, 2048]) against the oracle on every 16th image."""
+    specs = wl.batch_specs(256, seed=0)
+    imgs = [wl.make(k, H, W, seed=s, **kw) for (H, W, k, kw, s) in specs]
+    outs = ccl.label_batch([to_dev(im) for im in imgs], 8)
+    torch.cuda.synchronize()
+    for i in range(0, 256, 16):
+        assert np.array_equal(outs[i].cpu().numpy(), oracle_label(imgs[i], 8)), i
+
+
+def test_plan_and_graph_replay(ccl):
+    """A prepared batch equals label_batch and the oracle; captured into a
+    graph, every replay (with eager work and new pixels in between) equals
+    the eager result for the pixels of that replay."""
+    specs = wl.batch_specs(12, seed=5, lo=40, hi=400)
+    imgs = [wl.make(k, H, W, seed=s, **kw) for (H, W, k, kw, s) in specs]
+    conns = [4 if i % 2 else 8 for i in range(len(imgs))]
+    devs = [to_dev(im) for im in imgs]
+    plan = ccl.Plan(devs, conns)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for im, c, o in zip(imgs, conns, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle_label(im, c))
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run(stream=s)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.run()
+    for rep in range(3):
+        new = [wl.bernoulli(im.shape[0], im.shape[1], 0.3 + 0.2 * rep, seed=rep * 100 + i)
+               for i, im in enumerate(imgs)]
+        for d, n in zip(devs, new):
+            d.copy_(torch.from_numpy(n))
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        del junk
+        for n, c, o in zip(new, conns, outs):
+            assert np.array_equal(o.cpu().numpy(), oracle_label(n, c)), rep
+    plan.close()
