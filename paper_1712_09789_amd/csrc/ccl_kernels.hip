@@ -101,8 +101,12 @@ __device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Packed root of x.  Halves the path on the way: every store writes the
-// grandparent, whose key is smaller, so entries only ever decrease.
+// Packed root of x.  Halves the path on the way: x takes its grandparent,
+// whose key is smaller.  The halving write is an atomic min, not a store: a
+// stale grandparent read before another thread pointed x straight at the
+// root must not overwrite that pointer (the run table and the border slots
+// rely on every run holding its root after the unification passes).  Along
+// a path keys only decrease, so the root is the smallest value x can hold.
 __device__ uint32_t pfind(uint32_t* P, uint32_t x)
 {
     uint32_t v = lds_ld(P + x);
@@ -110,7 +114,7 @@ __device__ uint32_t pfind(uint32_t* P, uint32_t x)
         const uint32_t p = pk_id(v);
         const uint32_t w = lds_ld(P + p);
         if (pk_id(w) == p) return w;
-        lds_st(P + x, w);
+        __hip_atomic_fetch_min(P + x, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         x = pk_id(w);
         v = lds_ld(P + x);
     }
