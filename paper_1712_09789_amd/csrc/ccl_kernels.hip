@@ -155,10 +155,11 @@ __device__ __forceinline__ uint64_t g_ld(const uint64_t* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ Root g_find(uint64_t* F, uint32_t n)
+// Root of n, given v = F[n] already loaded.  Halves the path on the way
+// (an atomic min, so a concurrent link to a smaller key is never undone).
+__device__ Root g_find_from(uint64_t* F, uint32_t n, uint64_t v)
 {
     while (true) {
-        uint64_t v = g_ld(F + n);
         uint32_t p = (uint32_t)v;
         if (p == n) return Root{n, (uint32_t)(v >> 32)};
         uint64_t vp = g_ld(F + p);
@@ -166,24 +167,19 @@ __device__ Root g_find(uint64_t* F, uint32_t n)
         if (pp == p) return Root{p, (uint32_t)(vp >> 32)};
         __hip_atomic_fetch_min(F + n, vp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         n = pp;
+        v = g_ld(F + n);
     }
 }
 
-__device__ Root g_find_ro(const uint64_t* F, uint32_t n)
-{
-    while (true) {
-        uint64_t v = g_ld(F + n);
-        uint32_t p = (uint32_t)v;
-        if (p == n) return Root{n, (uint32_t)(v >> 32)};
-        n = p;
-    }
-}
-
+// The paper's merge on the HBM forest.  The first loads of both finds are
+// issued together, so a union whose nodes are still roots costs one round
+// trip before the link instead of two.
 __device__ void g_union(uint64_t* F, uint32_t a, uint32_t b)
 {
     while (true) {
-        Root ra = g_find(F, a);
-        Root rb = g_find(F, b);
+        const uint64_t va = g_ld(F + a), vb = g_ld(F + b);
+        Root ra = g_find_from(F, a, va);
+        Root rb = g_find_from(F, b, vb);
         if (ra.node == rb.node) return;
         if (ra.key < rb.key) { Root t = ra; ra = rb; rb = t; }
         // ra has the larger key: link it under rb
@@ -287,10 +283,10 @@ __device__ __forceinline__ void slot_xy(int s, int& x, int& y)
     else { x = TW - 1; y = s - 2 * TW - TILE_ROWS; }
 }
 
-// Run-table entry flags: the run's component touches the tile border (low
-// bits = representative border slot) / this run is that component's root.
+// Run-table entry flag: the run's component touches the tile border (low
+// bits = its representative border slot; otherwise the entry is the tile
+// position of the component's smallest pixel).
 constexpr uint16_t RT_BORDER = 0x8000;
-constexpr uint16_t RT_ROOT = 0x4000;
 constexpr uint32_t REP_TAG = 0x80000000u;
 
 // ---------------------------------------------------------------------------
@@ -301,13 +297,27 @@ constexpr uint32_t REP_TAG = 0x80000000u;
 // images of a batch
 // ---------------------------------------------------------------------------
 
+// The batch tables are read-only while the labelling kernels run and are
+// indexed by workgroup-uniform values: they are read through the constant
+// address space, so the loads go to the scalar unit and do not queue behind
+// (or hold up) the vector loads of tile data in flight.
+template <typename V>
+__device__ __forceinline__ V ld_uniform(const V* p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) V*)p;
+#else
+    return *p;  // host pass: never executed
+#endif
+}
+
 __device__ __forceinline__ ImageArgs batch_image(const BatchArgs& b, int i)
 {
-    return b.n == 1 ? b.one : b.imgs[i];
+    return b.n == 1 ? b.one : ld_uniform(b.imgs + i);
 }
 __device__ __forceinline__ int tile_image(const BatchArgs& b, int64_t T)
 {
-    return b.n == 1 ? 0 : b.tile_img[T];
+    return b.n == 1 ? 0 : ld_uniform(b.tile_img + T);
 }
 
 // Largest i with off[i] <= x, for off[0] = 0 <= x < off[n].
@@ -544,13 +554,13 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
     }
 
     // Run table: interior components store their root's tile key; border
-    // components store their representative slot (and mark the root run).
+    // components store their representative slot.
     uint16_t* rt = ws.runtab + T * RUNTAB_PER_TILE;
     for (uint32_t id = tid; id < R; id += NT) {
         const uint32_t v = lds_ld(sh.P + id);
         uint16_t ent;
         if (v & REP_TAG) {
-            ent = (uint16_t)(RT_BORDER | RT_ROOT | (NSLOTS - 1 - pk_id(v)));
+            ent = (uint16_t)(RT_BORDER | (NSLOTS - 1 - pk_id(v)));
         } else {
             const uint32_t w = pk_id(v) == id ? v : lds_ld(sh.P + pk_id(v));
             ent = (w & REP_TAG) ? (uint16_t)(RT_BORDER | (NSLOTS - 1 - pk_id(w)))
@@ -701,32 +711,47 @@ __global__ __launch_bounds__(NTB) void k_block(BatchArgs b, Workspace ws)
     __shared__ int32_t S[BN];            // the group's slot tables (node ids, -1 = bg)
     __shared__ uint32_t isrep[BN / 32];  // group indices that are forest nodes
     const int tid = threadIdx.x;
-    const int img = b.n == 1 ? 0 : b.group_img[blockIdx.x];
+    const int img = b.n == 1 ? 0 : ld_uniform(b.group_img + blockIdx.x);
     const ImageArgs a = batch_image(b, img);
-    const int g = (int)(blockIdx.x - (b.n == 1 ? 0 : b.group_off[img]));
+    const int g = (int)(blockIdx.x - (b.n == 1 ? 0 : ld_uniform(b.group_off + img)));
     const int nbx = (a.ntx + BX - 1) / BX;
     const int tx0 = (g % nbx) * BX, ty0 = (g / nbx) * BY;
     const int px0 = tx0 * TW, py0 = ty0 * TILE_ROWS;
 
-    for (int i = tid; i < BN / 32; i += NTB) isrep[i] = 0u;
-    __syncthreads();
-    // One pass over the group's slot tables and forest entries (independent
-    // loads); nodes are keyed by the position of their smallest pixel
-    // relative to the group origin (same order as raster position).
-    for (int li = tid; li < BN; li += NTB) {
+    // The group's slot tables and forest entries: all loads are issued before
+    // any is used (one round trip instead of one per pass).  Tiles past the
+    // image edge read the group's first tile and count as background.  Nodes
+    // are keyed by the position of their smallest pixel relative to the group
+    // origin (same order as raster position).
+    constexpr int PER = BN / NTB;
+    static_assert(BN % NTB == 0 && NTB % 64 == 0, "whole wavefronts per pass");
+    int32_t nd[PER];
+    uint32_t fk[PER];
+    int64_t ix[PER];
+    bool in[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int li = tid + k * NTB;
         const int ti = li / NSLOTS, sl = li % NSLOTS;
         const int tx = tx0 + ti % BX, ty = ty0 + ti / BX;
-        int32_t node = -1;
-        if (tx < a.ntx && ty < a.nty) {
-            const int64_t base = (a.tbase + (int64_t)ty * a.ntx + tx) * NSLOTS;
-            node = ws.slots[base + sl];
-            const uint64_t f = ws.forest[base + sl];
-            if (node == (int32_t)(base + sl)) {
-                uint32_t gy, gx;
-                divmod_w((uint32_t)(f >> 32), (uint32_t)a.W, a.wmagic, gy, gx);
-                P[li] = pk((gy - py0) * BPX + (gx - px0), li);
-                atomicOr(isrep + (li >> 5), 1u << (li & 31));
-            }
+        in[k] = tx < a.ntx && ty < a.nty;
+        ix[k] = (a.tbase + (int64_t)(in[k] ? ty : ty0) * a.ntx + (in[k] ? tx : tx0)) * NSLOTS + sl;
+        nd[k] = ws.slots[ix[k]];
+        fk[k] = (uint32_t)(ws.forest[ix[k]] >> 32);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int li = tid + k * NTB;
+        const int32_t node = in[k] ? nd[k] : -1;
+        const bool rep = node == (int32_t)ix[k];
+        // every entry gets a value; only those of representatives are read
+        uint32_t gy, gx;
+        divmod_w(fk[k], (uint32_t)a.W, a.wmagic, gy, gx);
+        P[li] = pk((gy - py0) * BPX + (gx - px0), li);
+        const uint64_t bal = __ballot(rep);
+        if ((tid & 63) == 0) {
+            isrep[li >> 5] = (uint32_t)bal;
+            isrep[(li >> 5) + 1] = (uint32_t)(bal >> 32);
         }
         S[li] = node;
     }
@@ -821,9 +846,9 @@ __global__ __launch_bounds__(NTB) void k_block(BatchArgs b, Workspace ws)
 template <int D>
 __global__ __launch_bounds__(SEAM_WG) void k_seam(BatchArgs b, Workspace ws)
 {
-    const int img = b.n == 1 ? 0 : b.seam_img[blockIdx.x];
+    const int img = b.n == 1 ? 0 : ld_uniform(b.seam_img + blockIdx.x);
     const ImageArgs a = batch_image(b, img);
-    const int64_t wg = blockIdx.x - (b.n == 1 ? 0 : b.seam_off[img]);
+    const int64_t wg = blockIdx.x - (b.n == 1 ? 0 : ld_uniform(b.seam_off + img));
     const int64_t gid = wg * SEAM_WG + threadIdx.x;
     const int nkh = (a.nty - 1) / BY, nkv = (a.ntx - 1) / BX;
     const int nbx = (a.ntx + BX - 1) / BX;
@@ -881,47 +906,64 @@ __global__ __launch_bounds__(SEAM_WG) void k_seam(BatchArgs b, Workspace ws)
 template <int D>
 struct FinalShared : Lines<D> {
     int32_t lab[Geo<D>::MAXR];             // final label of each run
-    int32_t fin[NSLOTS];                   // final label of each border component, by slot
+    int32_t fin[NSLOTS];                   // final label of the component at each border slot
     alignas(16) uint16_t ent[RUNTAB_PER_TILE];  // the tile's run table
 };
 static_assert(RUNTAB_PER_TILE == 8 * NT, "one 16-byte run-table load per thread");
 
-// Update of the global label map (Section 3.3).  Each border component takes
-// 1 + the key of its global root, every other component 1 + the raster
-// position of its local root; each label is written once.  With LOCAL_ONLY
-// the forest is read before any merge (every tile labelled as an image).
-template <int D, bool LOCAL_ONLY>
-__global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws)
+// Loads of one tile for k_final that depend on no other: the border slot of
+// this thread, the row masks and the whole run table (eight entries per
+// thread; entries past the run count are unused).
+struct FinalFetch {
+    int32_t node;
+    uint64_t m;
+    uint4 ent;
+};
+
+__device__ __forceinline__ FinalFetch final_fetch(const Workspace& ws, int64_t T, int tid)
 {
-    __shared__ FinalShared<D> sh;
-    const int tid = threadIdx.x;
-    const int64_t T = blockIdx.x;  // global tile
+    static_assert(NSLOTS == NT, "one border slot per thread");
+    FinalFetch f;
+    f.node = ws.slots[T * NSLOTS + tid];
+    f.m = tid < TILE_ROWS ? ws.bits[T * TILE_ROWS + tid] : 0ull;
+    f.ent = reinterpret_cast<const uint4*>(ws.runtab + T * RUNTAB_PER_TILE)[tid];
+    return f;
+}
+
+// Update of the global label map (Section 3.3) for global tile T.  Each
+// border component takes 1 + the key of its global root, every other
+// component 1 + the raster position of its local root; each label is
+// written once.  With LOCAL_ONLY the forest is read before any merge (every
+// tile labelled as an image).
+template <int D, bool LOCAL_ONLY>
+__device__ void final_tile(const BatchArgs& b, const Workspace& ws, FinalShared<D>& sh,
+                           int64_t T, const FinalFetch& f, int tid)
+{
     const ImageArgs a = batch_image(b, tile_image(b, T));
     const int t = (int)(T - a.tbase);
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
-    if (tid < TILE_ROWS) sh.M[tid] = ws.bits[T * TILE_ROWS + tid];
+    // The first forest hop is issued before the line set-up, so the chase
+    // to the global root overlaps it.
+    uint64_t v = f.node >= 0 ? ws.forest[f.node] : 0;
+    if (tid < TILE_ROWS) sh.M[tid] = f.m;
     __syncthreads();
     build_lines<D>(sh, tid);
     const uint32_t R = sh.base[Geo<D>::NL];
-    const uint16_t* rt = ws.runtab + T * RUNTAB_PER_TILE;
-    const int64_t sbase = T * NSLOTS;
-
-    // the run table in one coalesced load (eight entries per thread)
-    if (8u * tid < R)
-        reinterpret_cast<uint4*>(sh.ent)[tid] = reinterpret_cast<const uint4*>(rt)[tid];
-    __syncthreads();
-    // global root of each border component, looked up once (by its root run)
-    for (uint32_t id = tid; id < R; id += NT) {
-        const uint16_t e = sh.ent[id];
-        if ((e & (RT_BORDER | RT_ROOT)) == (RT_BORDER | RT_ROOT)) {
-            const int rep = e & 0x3fff;
-            const uint32_t key = LOCAL_ONLY
-                                     ? (uint32_t)(g_ld(ws.forest + sbase + rep) >> 32)
-                                     : g_find_ro(ws.forest, (uint32_t)(sbase + rep)).key;
-            sh.fin[rep] = (int32_t)(key + 1u);
+    reinterpret_cast<uint4*>(sh.ent)[tid] = f.ent;
+    // Global root of the component at this border slot.  The slot names a
+    // forest node of that component (its tile representative, or the group
+    // root after the block merge); before any merge the node is the root.
+    if (f.node >= 0) {
+        if (!LOCAL_ONLY) {
+            uint32_t n = (uint32_t)f.node;
+            while ((uint32_t)v != n) {
+                n = (uint32_t)v;
+                v = ws.forest[n];
+            }
         }
+        sh.fin[tid] = (int32_t)((uint32_t)(v >> 32) + 1u);
     }
     __syncthreads();
     for (uint32_t id = tid; id < R; id += NT) {
@@ -929,7 +971,7 @@ __global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws)
         // border component: its global root; otherwise ID conversion of the
         // interior component's local root
         sh.lab[id] = (e & RT_BORDER)
-                         ? sh.fin[e & 0x3fff]
+                         ? sh.fin[e & 0x7fff]
                          : (int32_t)((int64_t)(gy0 + (int)(e / TW)) * a.W + gx0 + (int)(e % TW) + 1);
     }
     __syncthreads();
@@ -945,20 +987,39 @@ __global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws)
         const uint32_t m4 = (uint32_t)(sh.M[r] >> x0) & 15u;
         const uint32_t s4 = (uint32_t)(ls >> x0) & 15u;
         uint32_t cnt = sh.base[l] + popc64(ls & ~(~0ull << x0));  // runs starting left of x0
-        int32_t v[4];
+        int32_t o[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             cnt += (s4 >> k) & 1u;
             // a foreground pixel has its run start at or left of it, so cnt >= 1
-            v[k] = ((m4 >> k) & 1u) ? sh.lab[cnt ? cnt - 1 : 0] : 0;
+            o[k] = ((m4 >> k) & 1u) ? sh.lab[cnt ? cnt - 1 : 0] : 0;
         }
         int32_t* dst = a.labels + (int64_t)gy * a.W + gx0 + x0;
         if (a.vec_out && x0 + 4 <= xmax) {
-            *reinterpret_cast<int4*>(dst) = make_int4(v[0], v[1], v[2], v[3]);
+            *reinterpret_cast<int4*>(dst) = make_int4(o[0], o[1], o[2], o[3]);
         } else {
             const int n = xmax - x0 < 4 ? xmax - x0 : 4;
-            for (int k = 0; k < n; ++k) dst[k] = v[k];
+            for (int k = 0; k < n; ++k) dst[k] = o[k];
         }
+    }
+}
+
+// Persistent over tiles like k_local: each workgroup takes tiles blockIdx.x,
+// + gridDim.x, ... and issues the next tile's loads before labelling the
+// current one.
+template <int D, bool LOCAL_ONLY>
+__global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws)
+{
+    __shared__ FinalShared<D> sh;
+    const int tid = threadIdx.x;
+    int64_t T = blockIdx.x;
+    if (T >= b.ntiles) return;
+    FinalFetch next = final_fetch(ws, T, tid);
+    for (; T < b.ntiles; T += gridDim.x) {
+        const FinalFetch cur = next;
+        if (T + gridDim.x < b.ntiles) next = final_fetch(ws, T + gridDim.x, tid);
+        final_tile<D, LOCAL_ONLY>(b, ws, sh, T, cur, tid);
+        __syncthreads();
     }
 }
 
@@ -1004,6 +1065,7 @@ static unsigned resident_blocks(K kernel, int threads)
 
 int64_t image_groups(int ntx, int nty)
 {
+    if (ntx == 1 && nty == 1) return 0;  // nothing to merge
     return (int64_t)((ntx + BX - 1) / BX) * ((nty + BY - 1) / BY);
 }
 
@@ -1026,12 +1088,14 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
     k_local<D><<<lgrid, NT, 0, st>>>(b, ws);
     timer_end(timer, KIND_LOCAL, st);
     if (local_only) {
+        const unsigned fgrid =
+            (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, true>, NT));
         timer_begin(timer, KIND_FINAL, st);
-        k_final<D, true><<<(unsigned)b.ntiles, NT, 0, st>>>(b, ws);
+        k_final<D, true><<<fgrid, NT, 0, st>>>(b, ws);
         timer_end(timer, KIND_FINAL, st);
         return hipGetLastError();
     }
-    // a single-tile image has no seams
+    // single-tile images have no merge group (and no seams)
     if (b.ngroups > 0) {
         timer_begin(timer, KIND_BLOCK, st);
         k_block<D><<<(unsigned)b.ngroups, NTB, 0, st>>>(b, ws);
@@ -1042,8 +1106,10 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
         k_seam<D><<<(unsigned)b.nseamwg, SEAM_WG, 0, st>>>(b, ws);
         timer_end(timer, KIND_SEAM, st);
     }
+    const unsigned fgrid =
+        (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, false>, NT));
     timer_begin(timer, KIND_FINAL, st);
-    k_final<D, false><<<(unsigned)b.ntiles, NT, 0, st>>>(b, ws);
+    k_final<D, false><<<fgrid, NT, 0, st>>>(b, ws);
     timer_end(timer, KIND_FINAL, st);
     return hipGetLastError();
 }
