@@ -5,8 +5,11 @@ single-image sweep (Bernoulli foreground at p = 0.1/0.3/0.5/0.7/0.9, blobs =
 smoothed uniform noise thresholded at the median with sigma 4/16) under 4- and
 8-connectivity: 14 images, each with its own input and label buffers, visited
 in rotation so that successive steps do not find their data in the 256 MB
-Infinity Cache.  A step labels one image (all three kernels).  Inputs are
+Infinity Cache.  A step labels one image (all four kernels).  Inputs are
 resident in HBM before timing starts; host<->device copies are not timed.
+Besides the aggregate rate over the timed steps, the per-step median, minimum
+and 99th percentile (events between steps) and the rate of the library's copy
+kernel (the achievable HBM bandwidth on the box) are reported.
 
 The result is only reported as exact if every image's labels equal the CPU
 checker's (element-by-element, after a warm-up run), which is also timed on
@@ -14,7 +17,9 @@ one host core as the CPU baseline.
 
 Also reported (secondary): the 8192 x 8192 images (Bernoulli p = 0.5 and the
 adversarial spiral / serpentine / checkerboard / full set), as path
-throughput and fraction of the 8 TB/s HBM peak.
+throughput and fraction of the 8 TB/s HBM peak; a batch of 256 mixed-size
+images (one batched call against per-image calls, and the oracle on every
+host core); the serving loop at saturation and at half and 0.8 of it.
 
 Prints ONE JSON line.
 """
@@ -182,6 +187,70 @@ def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_byt
         fh.write("\n".join(lines) + "\n")
 
 
+def step_distribution(ccl, torch, devs, steps):
+    """Duration of each of `steps` steps from an event recorded between
+    consecutive steps: median, min and 99th percentile in microseconds."""
+    st = torch.cuda.current_stream()
+    n = len(devs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    for i in range(steps):
+        img, out, conn = devs[i % n]
+        ccl.label(img, conn, out=out)
+        ev[i + 1].record(st)
+    torch.cuda.synchronize()
+    us = np.array([1e3 * ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return {"median": round(float(np.median(us)), 2), "min": round(float(us.min()), 2),
+            "p99": round(float(np.percentile(us, 99)), 2), "reps": steps}
+
+
+def copy_bandwidth(ccl, torch, dev, mib=256, reps=10):
+    """Read + write GB/s of the library's copy kernel over `mib` MiB: the
+    achievable HBM rate on this machine, next to the 8 TB/s peak."""
+    nbytes = mib << 20
+    src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    ccl.copy_bytes(src, dst)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        ccl.copy_bytes(src, dst)
+    e1.record(st)
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / reps / 1e3
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / secs / 1e9
+
+
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "usable": len(os.sched_getaffinity(0)), "model": model}
+
+
+def oracle_all_cores(imgs, conn):
+    """The oracle over a list of images, one image per worker thread on every
+    usable core (the C routine releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as pool:
+        outs = list(pool.map(lambda im: oracle.oracle_label(im, conn), imgs))
+    return outs, time.perf_counter() - t0, cores
+
+
 def bench_batch(ccl, torch, dev, check=True, n=256, reps=5):
     """256 uint8 images, sides log-uniform in [64, 2048], half Bernoulli and
     half blobs at random density, 8-connectivity: one ccl_label_batch call
@@ -234,12 +303,14 @@ def bench_batch(ccl, torch, dev, check=True, n=256, reps=5):
         plan.run()
     t_graph = timed(g.replay)
     exact = None
+    cpu = None
     if check:
-        import oracle
         batch()
         torch.cuda.synchronize()
-        exact = all(np.array_equal(outs[i].cpu().numpy(), oracle.oracle_label(imgs[i], 8))
-                    for i in range(0, n, 8))
+        wants, cpu_secs, cores = oracle_all_cores(imgs, 8)
+        exact = all(np.array_equal(outs[i].cpu().numpy(), wants[i]) for i in range(0, n, 8))
+        cpu = {"Gpx/s": round(px / cpu_secs / 1e9, 4), "cores": cores, "kind": "oracle",
+               "sample": "the whole batch once, one image per worker thread"}
     return {"images": n, "Mpx": round(px / 1e6, 2),
             "batch_ms": round(1e3 * t_batch, 3), "per_image_ms": round(1e3 * t_single, 3),
             "batch_Gpx/s": round(px / t_batch / 1e9, 1),
@@ -248,7 +319,8 @@ def bench_batch(ccl, torch, dev, check=True, n=256, reps=5):
             "graph_Gpx/s": round(px / t_graph / 1e9, 1),
             "speedup": round(t_single / t_batch, 3),
             "speedup_graph": round(t_single / t_graph, 3),
-            "exact_sampled": exact}
+            "exact_sampled": exact,
+            "oracle_all_cores": cpu}
 
 
 def bench_serving(torch, dev, n=2000, seed=0):
@@ -383,7 +455,8 @@ def main():
         cpu = {"value": round(cpu_px / cpu_secs / 1e9, 5), "unit": "Gpixel/s", "cores": 1,
                "kind": "oracle",
                "sample": f"{len(cases)} images of {size}x{size} (every headline case once), "
-                         f"single thread pinned to one core, {cpu_secs:.1f} s total"}
+                         f"single thread pinned to one core, {cpu_secs:.1f} s total",
+               "host": host_cpu()}
 
     # timed region (headline value); then a region with events around every
     # kernel (per-kernel breakdown) and one with events around the dominant
@@ -394,6 +467,8 @@ def main():
     kavg = {k: round(1e3 * v[0] / v[1], 2) for k, v in kern.items() if v[1]}
     dom = max(("local", "final"), key=lambda k: kavg.get(k, 0.0))
     _, kdom = time_rotation(ccl, torch, devs, args.steps, args.warmup, timing=[dom])
+    dist = step_distribution(ccl, torch, devs, max(args.steps, 20))
+    copy_gbs = copy_bandwidth(ccl, torch, dev)
     px = size * size
     value = args.steps * px / secs / 1e9
     ms_step = 1e3 * secs / args.steps
@@ -426,7 +501,10 @@ def main():
                                "{.1,.3,.5,.7,.9} and median-thresholded blobs sigma {4,16}; "
                                "connectivity 4 and 8; 14 resident buffer sets in rotation",
                    "tile": list(ccl.tile_shape())},
+        "step_us": dist,
         "path_hbm_frac": round(PATH_BYTES_PER_PX * value / HBM_PEAK_GBS, 4),
+        "copy_GBs": round(copy_gbs, 1),
+        "path_copy_frac": round(PATH_BYTES_PER_PX * value / copy_gbs, 4),
         "kernel_avg_us": kavg,
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
