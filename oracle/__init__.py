@@ -75,3 +75,39 @@ def oracle_label(img: np.ndarray, connectivity: int = 8) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle_label failed with status {rc}")
     return out
+
+
+# Per-component statistics: the quantities the paper names as the use of a
+# labelling (the size and the location of each connected set, Section 1),
+# written out from their definitions over the labelled pixels.
+STATS_DTYPE = np.dtype([("label", np.int32), ("area", np.int32),
+                        ("x_min", np.int32), ("y_min", np.int32),
+                        ("x_max", np.int32), ("y_max", np.int32),
+                        ("sum_x", np.int64), ("sum_y", np.int64)])
+
+
+def oracle_stats(img: np.ndarray, connectivity: int = 8) -> np.ndarray:
+    """Statistics of every connected component, in ascending label order.
+
+    For the component with label L (1 + its smallest raster position):
+    area = number of its pixels; x_min/x_max, y_min/y_max = the smallest and
+    largest column and row among them (an inclusive bounding box); sum_x,
+    sum_y = the sums of their columns and rows (centroid = sum / area)."""
+    lab = oracle_label(img, connectivity)
+    ys, xs = np.nonzero(lab)
+    labels, inv, area = np.unique(lab[ys, xs], return_inverse=True, return_counts=True)
+    n = len(labels)
+    out = np.zeros(n, dtype=STATS_DTYPE)
+    out["label"] = labels
+    out["area"] = area
+    big = np.iinfo(np.int32).max
+    for field, coord, fn, init in (("x_min", xs, np.minimum, big), ("y_min", ys, np.minimum, big),
+                                   ("x_max", xs, np.maximum, -1), ("y_max", ys, np.maximum, -1)):
+        acc = np.full(n, init, dtype=np.int64)
+        fn.at(acc, inv, coord)
+        out[field] = acc
+    for field, coord in (("sum_x", xs), ("sum_y", ys)):
+        acc = np.zeros(n, dtype=np.int64)
+        np.add.at(acc, inv, coord.astype(np.int64))
+        out[field] = acc
+    return out
