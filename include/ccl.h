@@ -106,6 +106,40 @@ int ccl_plan_run(ccl_plan* plan, void* stream);
 int ccl_plan_destroy(ccl_plan* plan);
 
 /*
+ * Statistics of one connected component.  The paper's introduction names
+ * what a labelling is for: the size and the location of each connected set;
+ * these are that size, its box and the sums that give its centroid.
+ */
+typedef struct {
+    int32_t label;   /* 1 + raster position of the component's smallest pixel */
+    int32_t area;    /* number of pixels                                       */
+    int32_t x_min;   /* inclusive bounding box: smallest and largest column    */
+    int32_t y_min;   /* and row among the component's pixels                   */
+    int32_t x_max;
+    int32_t y_max;
+    int64_t sum_x;   /* sum of the pixels' columns (centroid x = sum_x / area) */
+    int64_t sum_y;   /* sum of the pixels' rows    (centroid y = sum_y / area) */
+} ccl_component;     /* 40 bytes */
+
+/*
+ * Label one image (as ccl_label) and compute the statistics of every
+ * component.
+ *   comps     device array of `capacity` entries, caller-owned.  Entry i
+ *             describes the component with the i-th smallest label, so the
+ *             array is sorted by label.  Entries [0, min(*count, capacity))
+ *             are written; the rest are untouched.
+ *   capacity  entries comps holds (>= 0; 0 computes the count only).
+ *   count     device int64: the number of components, also when it exceeds
+ *             capacity (call again with a larger array to get them all).
+ * Other arguments and errors as ccl_label; additionally CCL_ERR_INVALID_ARG
+ * for a null count, capacity < 0, or a null comps with capacity > 0.  An
+ * empty image writes *count = 0.  Enqueued on `stream` like ccl_label.
+ */
+int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                    int32_t connectivity, int32_t* labels, ccl_component* comps,
+                    int64_t capacity, int64_t* count, void* stream);
+
+/*
  * Debugging aid for the local step alone (Section 3.1): every tile is
  * labelled as if it were a separate image, and each foreground pixel gets
  * 1 + the raster position (in the whole image) of the smallest pixel of its

@@ -11,6 +11,7 @@ import ctypes
 import os
 from typing import Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -20,6 +21,12 @@ CCL_OK = 0
 STATUS_NAMES = {0: "CCL_OK", -1: "CCL_ERR_INVALID_ARG", -2: "CCL_ERR_TOO_LARGE",
                 -3: "CCL_ERR_OUT_OF_MEMORY", -4: "CCL_ERR_HIP"}
 KERNEL_KINDS = ("local", "seam", "final", "copy", "block")
+# Layout of ccl_component (include/ccl.h), 40 bytes per component.
+COMPONENT_DTYPE = np.dtype([("label", np.int32), ("area", np.int32),
+                            ("x_min", np.int32), ("y_min", np.int32),
+                            ("x_max", np.int32), ("y_max", np.int32),
+                            ("sum_x", np.int64), ("sum_y", np.int64)])
+assert COMPONENT_DTYPE.itemsize == 40
 
 
 class CCLError(RuntimeError):
@@ -44,6 +51,8 @@ def _load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [vp, i32, i32, i64, i32, vp, vp]
+    lib.ccl_label_stats.restype = ctypes.c_int
+    lib.ccl_label_stats.argtypes = [vp, i32, i32, i64, i32, vp, vp, i64, vp, vp]
     lib.ccl_label_batch.restype = ctypes.c_int
     lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), i32, vp]
     lib.ccl_tile_cols.restype = i32
@@ -119,6 +128,43 @@ def label(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | None = N
     _check(_lib.ccl_label(img.data_ptr(), H, W, pitch, int(connectivity), out.data_ptr(),
                           _stream_handle(stream)))
     return out
+
+
+def max_components(H: int, W: int, connectivity: int = 8) -> int:
+    """Most components an H x W image can have (isolated pixels on a
+    checkerboard for 4-connectivity, on every other row and column for 8)."""
+    if connectivity == 4:
+        return (H * W + 1) // 2
+    return ((H + 1) // 2) * ((W + 1) // 2)
+
+
+def label_stats(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | None = None,
+                capacity: int | None = None, stream=None):
+    """Labels plus the statistics of every component (ccl_label_stats).
+
+    Returns (labels, comps, count): comps is a uint8 device tensor holding
+    `capacity` ccl_component records (sorted by label; default capacity =
+    the most components the image can have), count a one-element int64
+    device tensor.  ``components_to_numpy`` copies the valid records out."""
+    H, W, pitch = _image_args(img)
+    out = _out_for(img, out)
+    if capacity is None:
+        capacity = max_components(H, W, connectivity)
+    comps = torch.empty(capacity * COMPONENT_DTYPE.itemsize, dtype=torch.uint8,
+                        device=img.device)
+    count = torch.empty(1, dtype=torch.int64, device=img.device)
+    _check(_lib.ccl_label_stats(img.data_ptr(), H, W, pitch, int(connectivity), out.data_ptr(),
+                                comps.data_ptr(), int(capacity), count.data_ptr(),
+                                _stream_handle(stream)))
+    return out, comps, count
+
+
+def components_to_numpy(comps: torch.Tensor, count: torch.Tensor) -> np.ndarray:
+    """The valid records of a label_stats result as a numpy structured array
+    (synchronises with the device)."""
+    n = min(int(count.item()), comps.numel() // COMPONENT_DTYPE.itemsize)
+    raw = comps[:n * COMPONENT_DTYPE.itemsize].cpu().numpy()
+    return raw.view(COMPONENT_DTYPE).copy()
 
 
 def label_local(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | None = None,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -265,22 +266,38 @@ static int bind_class(const std::vector<ImageArgs>& imgs, const ClassLayout& L, 
 // travels in the kernel arguments; several get a device table (copied into
 // the head of the workspace) that maps global tiles, merge groups and seam
 // workgroups back to their image.
+// Caller's outputs of the statistics path.
+struct StatsOut {
+    ccl_component* comps;
+    int64_t capacity;
+    int64_t* count;
+};
+
 static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, bool local_only,
-                     const char* who)
+                     const char* who, const StatsOut* so = nullptr)
 {
     if (imgs.empty()) return CCL_OK;
     ClassLayout L;
     int rc = layout_class(imgs, conn, L, who);
     if (rc != CCL_OK) return rc;
+    const int64_t label_bytes = align256(L.bytes());
     void* base = nullptr;
-    rc = get_workspace(L.bytes(), st, &base);
+    rc = get_workspace(label_bytes + (so ? stats_workspace_bytes(L.ntiles) : 0), st, &base);
     if (rc != CCL_OK) return rc;
     BatchArgs b;
     Workspace ws;
     rc = bind_class(imgs, L, base, local_only, st, b, ws, who);
     if (rc != CCL_OK) return rc;
+    StatsWs sw{};
+    if (so) {
+        sw = carve_stats(static_cast<char*>(base) + label_bytes, L.ntiles);
+        sw.comps = reinterpret_cast<CompStats*>(so->comps);
+        sw.capacity = so->capacity;
+        sw.count = so->count;
+    }
     hipError_t e = launch_index(b, st);
-    if (e == hipSuccess) e = launch_label(b, conn, ws, st, active_timer(), local_only);
+    if (e == hipSuccess)
+        e = launch_label(b, conn, ws, st, active_timer(), local_only, so ? &sw : nullptr);
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
     return CCL_OK;
 }
@@ -297,6 +314,10 @@ static int label_one(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, in
 }  // namespace ccl
 
 using namespace ccl;
+
+static_assert(sizeof(CompStats) == sizeof(ccl_component) &&
+                  offsetof(CompStats, sum_x) == offsetof(ccl_component, sum_x),
+              "statistics layout");
 
 // A prepared batch: own device memory, tables filled, ready to launch.
 struct ccl_plan {
@@ -318,6 +339,31 @@ int ccl_label(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
     g_err.clear();
     return label_one(img, H, W, pitch_bytes, connectivity, labels,
                      static_cast<hipStream_t>(stream), false, "ccl_label");
+}
+
+int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                    int32_t connectivity, int32_t* labels, ccl_component* comps,
+                    int64_t capacity, int64_t* count, void* stream)
+{
+    g_err.clear();
+    const char* who = "ccl_label_stats";
+    int rc = validate(img, H, W, pitch_bytes, connectivity, labels, who);
+    if (rc != CCL_OK) return rc;
+    if (!count) return fail(CCL_ERR_INVALID_ARG, "%s: null count pointer", who);
+    if (capacity < 0) return fail(CCL_ERR_INVALID_ARG, "%s: capacity %lld < 0", who,
+                                  (long long)capacity);
+    if (capacity > 0 && !comps)
+        return fail(CCL_ERR_INVALID_ARG, "%s: null component array with capacity %lld", who,
+                    (long long)capacity);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (H == 0 || W == 0) {
+        hipError_t e = launch_zero_count(count, st);
+        if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
+        return CCL_OK;
+    }
+    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, connectivity, labels));
+    StatsOut so{comps, capacity, count};
+    return run_batch(one, connectivity, st, false, who, &so);
 }
 
 int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,

@@ -77,6 +77,55 @@ inline Workspace carve_workspace(void* base, int64_t ntiles)
     return ws;
 }
 
+// Per-component statistics (same layout as ccl_component in ccl.h).
+struct CompStats {
+    int32_t label;
+    int32_t area;
+    int32_t x_min, y_min, x_max, y_max;
+    int64_t sum_x, sum_y;
+};
+
+// Statistics workspace and outputs of one image.  Components are numbered in
+// raster order of their smallest pixel: the count of such pixels per
+// (image row, tile column) segment is scanned, and a component's number is
+// the scanned count of its segment plus the smallest pixels left of it there.
+constexpr int SCAN_T = 1024;                // scan workgroup size
+constexpr int SCAN_BLK = 4 * SCAN_T;        // segments per first-level scan block
+struct StatsWs {
+    uint64_t* rootbits;  // [ntiles][TILE_ROWS] smallest pixels of components, by tile row
+    uint32_t* seg;       // [ntiles * TILE_ROWS] per segment: count, then exclusive scan in its block
+    uint32_t* bsum;      // [nblk] segments' total per scan block
+    uint32_t* boff;      // [nblk] exclusive scan of bsum
+    int64_t nseg, nblk;
+    CompStats* comps;    // caller's output [capacity]
+    int64_t capacity;
+    int64_t* count;      // caller's output: number of components
+};
+
+inline int64_t stats_workspace_bytes(int64_t ntiles)
+{
+    auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    const int64_t nseg = ntiles * TILE_ROWS, nblk = (nseg + SCAN_BLK - 1) / SCAN_BLK;
+    return up(nseg * 8) + up(nseg * 4) + 2 * up(nblk * 4);
+}
+
+inline StatsWs carve_stats(void* base, int64_t ntiles)
+{
+    auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    char* p = static_cast<char*>(base);
+    StatsWs s{};
+    s.nseg = ntiles * TILE_ROWS;
+    s.nblk = (s.nseg + SCAN_BLK - 1) / SCAN_BLK;
+    s.rootbits = reinterpret_cast<uint64_t*>(p);
+    p += up(s.nseg * 8);
+    s.seg = reinterpret_cast<uint32_t*>(p);
+    p += up(s.nseg * 4);
+    s.bsum = reinterpret_cast<uint32_t*>(p);
+    p += up(s.nblk * 4);
+    s.boff = reinterpret_cast<uint32_t*>(p);
+    return s;
+}
+
 enum { KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, KIND_BLOCK = 4, NKINDS = 5 };
 
 struct KernelTimer;  // host-side event recorder, null when timing is off
@@ -91,8 +140,12 @@ constexpr int SEAM_WG = 256;                 // k_seam workgroup size
 // k_index: fills the image-of-tile/group/seam-workgroup tables of a batch
 // (n > 1); must precede launch_label on the same stream.
 hipError_t launch_index(const BatchArgs& b, hipStream_t st);
+// With `stats` (a single image only) k_final also records the smallest
+// pixels of components, and the statistics kernels follow it.
 hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
-                        KernelTimer* timer, bool local_only);
+                        KernelTimer* timer, bool local_only, const StatsWs* stats = nullptr);
+// Writes *count = 0 (an empty image has no components).
+hipError_t launch_zero_count(int64_t* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,
                        KernelTimer* timer);
 

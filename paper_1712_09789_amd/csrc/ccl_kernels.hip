@@ -261,6 +261,21 @@ __device__ __forceinline__ uint32_t run_key(const Lines<D>& sh, int l, int a, in
     return top ? (uint32_t)(2 * l * TW + ctz64(top)) : (uint32_t)((2 * l + 1) * TW + a);
 }
 
+// Run list: RL[id] = start column | line << 6, for every run of the tile.
+// Thread tid takes one window of Geo<D>::WIN columns of one line.  Needs
+// build_lines; the caller synchronises before RL is read.
+template <int D>
+__device__ __forceinline__ void list_runs(const Lines<D>& sh, uint16_t* RL, int tid)
+{
+    using G = Geo<D>;
+    static_assert(G::WIN <= 16, "column windows fit a 32-bit word");
+    const int wl = tid / G::TPL, wlo = (tid % G::TPL) * G::WIN;
+    const uint64_t ls = sh.LS[wl];
+    uint32_t id = sh.base[wl] + popc64(ls & ~(~0ull << wlo));
+    for (uint32_t r = (uint32_t)(ls >> wlo) & ((1u << G::WIN) - 1u); r; r &= r - 1u, ++id)
+        RL[id] = (uint16_t)((__builtin_ctz(r) + wlo) | (wl << 6));
+}
+
 template <int D>
 struct LocalShared : Lines<D> {
     uint32_t P[Geo<D>::MAXR];    // parent of each run, packed (key << 16) | id
@@ -397,16 +412,10 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
     // tid + 256, ...) so that every lane has work; only two cheap passes walk
     // the bits of a column window: the run list and the refinement edge list.
     const uint32_t R = sh.base[G::NL];
-    static_assert(G::WIN <= 16, "column windows fit a 32-bit word");
     const int wl = tid / G::TPL;              // this thread's line
     const int wlo = (tid % G::TPL) * G::WIN;  // and first column of its window
     constexpr uint32_t WMASK = (1u << G::WIN) - 1u;
-    {
-        const uint64_t ls = sh.LS[wl];
-        uint32_t id = sh.base[wl] + popc64(ls & ~(~0ull << wlo));
-        for (uint32_t r = (uint32_t)(ls >> wlo) & WMASK; r; r &= r - 1u, ++id)
-            sh.RL[id] = (uint16_t)((__builtin_ctz(r) + wlo) | (wl << 6));
-    }
+    list_runs<D>(sh, sh.RL, tid);
     if (tid == 0) sh.nedges = 0u;
     __syncthreads();
 
@@ -905,6 +914,7 @@ __global__ __launch_bounds__(SEAM_WG) void k_seam(BatchArgs b, Workspace ws)
 
 template <int D>
 struct FinalShared : Lines<D> {
+    uint64_t rb[TILE_ROWS];                // with statistics: smallest pixels of components
     int32_t lab[Geo<D>::MAXR];             // final label of each run
     int32_t fin[NSLOTS];                   // final label of the component at each border slot
     alignas(16) uint16_t ent[RUNTAB_PER_TILE];  // the tile's run table
@@ -935,9 +945,9 @@ __device__ __forceinline__ FinalFetch final_fetch(const Workspace& ws, int64_t T
 // component 1 + the raster position of its local root; each label is
 // written once.  With LOCAL_ONLY the forest is read before any merge (every
 // tile labelled as an image).
-template <int D, bool LOCAL_ONLY>
-__device__ void final_tile(const BatchArgs& b, const Workspace& ws, FinalShared<D>& sh,
-                           int64_t T, const FinalFetch& f, int tid)
+template <int D, bool LOCAL_ONLY, bool STATS>
+__device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsWs& st,
+                           FinalShared<D>& sh, int64_t T, const FinalFetch& f, int tid)
 {
     const ImageArgs a = batch_image(b, tile_image(b, T));
     const int t = (int)(T - a.tbase);
@@ -947,7 +957,10 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, FinalShared<
     // The first forest hop is issued before the line set-up, so the chase
     // to the global root overlaps it.
     uint64_t v = f.node >= 0 ? ws.forest[f.node] : 0;
-    if (tid < TILE_ROWS) sh.M[tid] = f.m;
+    if (tid < TILE_ROWS) {
+        sh.M[tid] = f.m;
+        if (STATS) sh.rb[tid] = 0ull;
+    }
     __syncthreads();
     build_lines<D>(sh, tid);
     const uint32_t R = sh.base[Geo<D>::NL];
@@ -975,6 +988,26 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, FinalShared<
                          : (int32_t)((int64_t)(gy0 + (int)(e / TW)) * a.W + gx0 + (int)(e % TW) + 1);
     }
     __syncthreads();
+
+    // With statistics: mark the smallest pixel of every component that has
+    // it in this tile (label - 1 is its raster position), and count them per
+    // tile row for the numbering scan.
+    if (STATS) {
+        for (uint32_t id = tid; id < R; id += NT) {
+            uint32_t ry, rx;
+            divmod_w((uint32_t)sh.lab[id] - 1u, (uint32_t)a.W, a.wmagic, ry, rx);
+            ry -= (uint32_t)gy0;
+            rx -= (uint32_t)gx0;
+            if (ry < (uint32_t)TILE_ROWS && rx < (uint32_t)TW)
+                atomicOr(reinterpret_cast<unsigned long long*>(sh.rb + ry), 1ull << rx);
+        }
+        __syncthreads();
+        if (tid < TILE_ROWS) {
+            const uint64_t rb = sh.rb[tid];
+            st.rootbits[T * TILE_ROWS + tid] = rb;
+            st.seg[(int64_t)(ty * TILE_ROWS + tid) * a.ntx + tx] = popc64(rb);
+        }
+    }
 
     // write the labels: 16 threads per tile row, 4 pixels per thread
     const int xmax = a.W - gx0;  // pixels of this tile inside the image
@@ -1007,8 +1040,8 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, FinalShared<
 // Persistent over tiles like k_local: each workgroup takes tiles blockIdx.x,
 // + gridDim.x, ... and issues the next tile's loads before labelling the
 // current one.
-template <int D, bool LOCAL_ONLY>
-__global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws)
+template <int D, bool LOCAL_ONLY, bool STATS>
+__global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws, StatsWs st)
 {
     __shared__ FinalShared<D> sh;
     const int tid = threadIdx.x;
@@ -1018,10 +1051,181 @@ __global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws)
     for (; T < b.ntiles; T += gridDim.x) {
         const FinalFetch cur = next;
         if (T + gridDim.x < b.ntiles) next = final_fetch(ws, T + gridDim.x, tid);
-        final_tile<D, LOCAL_ONLY>(b, ws, sh, T, cur, tid);
+        final_tile<D, LOCAL_ONLY, STATS>(b, ws, st, sh, T, cur, tid);
         __syncthreads();
     }
 }
+
+// ---------------------------------------------------------------------------
+// per-component statistics
+// ---------------------------------------------------------------------------
+
+// Inclusive scan of v over the workgroup (SCAN_T threads); also returns the
+// workgroup total.  `wsum` holds SCAN_T / 64 words of LDS.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* wsum, uint32_t& total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t w = lane < SCAN_T / 64 ? wsum[lane] : 0u;
+#pragma unroll
+        for (int off = 1; off < SCAN_T / 64; off <<= 1) {
+            const uint32_t o = __shfl_up(w, off, 64);
+            if (lane >= off) w += o;
+        }
+        if (lane < SCAN_T / 64) wsum[lane] = w;
+    }
+    __syncthreads();
+    total = wsum[SCAN_T / 64 - 1];
+    const uint32_t r = inc + (wave > 0 ? wsum[wave - 1] : 0u);
+    __syncthreads();  // wsum may be reused by the caller
+    return r;
+}
+
+// First scan level: each block of SCAN_BLK segment counts becomes its
+// exclusive scan within the block; the block totals go to bsum.
+__global__ __launch_bounds__(SCAN_T) void k_scan1(StatsWs st)
+{
+    __shared__ uint32_t wsum[SCAN_T / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_BLK + 4 * (int64_t)threadIdx.x;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = base + k < st.nseg ? st.seg[base + k] : 0u;
+    const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+    uint32_t total;
+    uint32_t run = block_scan(mine, wsum, total) - mine;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < st.nseg) st.seg[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) st.bsum[blockIdx.x] = total;
+}
+
+// Second level (one workgroup): exclusive scan of the block totals, and the
+// number of components.
+__global__ __launch_bounds__(SCAN_T) void k_scan2(StatsWs st)
+{
+    __shared__ uint32_t wsum[SCAN_T / 64];
+    uint64_t carry = 0;
+    for (int64_t c0 = 0; c0 < st.nblk; c0 += SCAN_T) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint32_t v = i < st.nblk ? st.bsum[i] : 0u;
+        uint32_t total;
+        const uint32_t inc = block_scan(v, wsum, total);
+        if (i < st.nblk) st.boff[i] = (uint32_t)(carry + inc - v);
+        carry += total;
+    }
+    if (threadIdx.x == 0) *st.count = (int64_t)carry;
+}
+
+// Neutral values for the accumulating fields of every numbered component
+// that fits the caller's array.
+__global__ __launch_bounds__(256) void k_stats_init(StatsWs st)
+{
+    const int64_t n = *st.count < st.capacity ? *st.count : st.capacity;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        CompStats c;
+        c.label = 0;
+        c.area = 0;
+        c.x_min = c.y_min = INT32_MAX;
+        c.x_max = c.y_max = -1;
+        c.sum_x = c.sum_y = 0;
+        st.comps[i] = c;
+    }
+}
+
+// Sum of the positions of the set bits of m.
+__device__ __forceinline__ uint32_t bit_position_sum(uint64_t m)
+{
+    return popc64(m & 0xAAAAAAAAAAAAAAAAull) + 2u * popc64(m & 0xCCCCCCCCCCCCCCCCull) +
+           4u * popc64(m & 0xF0F0F0F0F0F0F0F0ull) + 8u * popc64(m & 0xFF00FF00FF00FF00ull) +
+           16u * popc64(m & 0xFFFF0000FFFF0000ull) + 32u * popc64(m & 0xFFFFFFFF00000000ull);
+}
+
+template <int D>
+struct StatsShared : Lines<D> {
+    uint16_t RL[Geo<D>::MAXR];
+};
+
+// Statistics of every run of a tile, added to its component's entry.  The
+// run's label is read back from the label map at its smallest pixel; the
+// component's number is the scanned count of its smallest pixel's segment
+// plus the smallest pixels left of it in that segment.
+template <int D>
+__global__ __launch_bounds__(NT) void k_stats(BatchArgs b, Workspace ws, StatsWs st)
+{
+    __shared__ StatsShared<D> sh;
+    const int tid = threadIdx.x;
+    const int64_t T = blockIdx.x;
+    const ImageArgs a = b.one;  // statistics are computed for a single image
+    const int t = (int)T;
+    const int tx = t % a.ntx, ty = t / a.ntx;
+    const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
+
+    if (tid < TILE_ROWS) sh.M[tid] = ws.bits[T * TILE_ROWS + tid];
+    __syncthreads();
+    build_lines<D>(sh, tid);
+    list_runs<D>(sh, sh.RL, tid);
+    __syncthreads();
+    const uint32_t R = sh.base[Geo<D>::NL];
+    for (uint32_t id = tid; id < R; id += NT) {
+        const uint32_t rec = sh.RL[id];
+        const int s0 = rec & 63, l = rec >> 6;
+        const int e = s0 + ctz64_or64(~(sh.LM[l] >> s0)) - 1;
+        uint32_t area, ymin, ymax, key;
+        uint64_t sx, sy;
+        if (!D) {
+            area = (uint32_t)(e - s0 + 1);
+            ymin = ymax = (uint32_t)l;
+            sx = (uint64_t)(s0 + e) * area / 2;
+            sy = (uint64_t)l * area;
+            key = (uint32_t)(l * TW + s0);
+        } else {
+            const uint64_t span = span_mask(s0, e);
+            const uint64_t top = sh.M[2 * l] & span, bot = sh.M[2 * l + 1] & span;
+            const uint32_t at = popc64(top), ab = popc64(bot);
+            area = at + ab;
+            ymin = top ? 2u * l : 2u * l + 1u;
+            ymax = bot ? 2u * l + 1u : 2u * l;
+            sx = (uint64_t)bit_position_sum(top) + bit_position_sum(bot);
+            sy = (uint64_t)(2 * l) * at + (uint64_t)(2 * l + 1) * ab;
+            key = top ? (uint32_t)(2 * l * TW + ctz64(top)) : (uint32_t)((2 * l + 1) * TW + s0);
+        }
+        const int64_t kpos = (int64_t)(gy0 + (int)(key / TW)) * a.W + gx0 + (int)(key % TW);
+        const int32_t L = a.labels[kpos];
+        if (L <= 0 || (int64_t)L > kpos + 1) continue;  // not a label of this pixel
+        uint32_t ry, rx;
+        divmod_w((uint32_t)L - 1u, (uint32_t)a.W, a.wmagic, ry, rx);
+        const int64_t sg = (int64_t)ry * a.ntx + rx / TW;
+        const int64_t rt = ((int64_t)(ry / TILE_ROWS) * a.ntx + rx / TW) * TILE_ROWS + ry % TILE_ROWS;
+        const int64_t num = (int64_t)st.seg[sg] + st.boff[sg / SCAN_BLK] +
+                            popc64(st.rootbits[rt] & ((1ull << (rx % TW)) - 1ull));
+        if (num >= st.capacity) continue;
+        CompStats* c = st.comps + num;
+        atomicAdd(&c->area, (int)area);
+        atomicMin(&c->x_min, gx0 + s0);
+        atomicMin(&c->y_min, gy0 + (int)ymin);
+        atomicMax(&c->x_max, gx0 + e);
+        atomicMax(&c->y_max, gy0 + (int)ymax);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&c->sum_x),
+                  (unsigned long long)(sx + (uint64_t)area * gx0));
+        atomicAdd(reinterpret_cast<unsigned long long*>(&c->sum_y),
+                  (unsigned long long)(sy + (uint64_t)area * gy0));
+        // the run that holds the component's smallest pixel writes the label
+        if (kpos == (int64_t)L - 1) c->label = L;
+    }
+}
+
+__global__ void k_zero_count(int64_t* count) { *count = 0; }
 
 // ---------------------------------------------------------------------------
 // copy kernel (bandwidth / counter calibration)
@@ -1079,8 +1283,9 @@ int64_t image_seam_items(int ntx, int nty, int H, int W, int conn)
 
 template <int D>
 static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_t st,
-                             KernelTimer* timer, bool local_only)
+                             KernelTimer* timer, bool local_only, const StatsWs* stats)
 {
+    const StatsWs none{};
     if (b.ntiles <= 0) return hipSuccess;
     const unsigned lgrid =
         (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_local<D>, NT));
@@ -1089,9 +1294,9 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
     timer_end(timer, KIND_LOCAL, st);
     if (local_only) {
         const unsigned fgrid =
-            (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, true>, NT));
+            (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, true, false>, NT));
         timer_begin(timer, KIND_FINAL, st);
-        k_final<D, true><<<fgrid, NT, 0, st>>>(b, ws);
+        k_final<D, true, false><<<fgrid, NT, 0, st>>>(b, ws, none);
         timer_end(timer, KIND_FINAL, st);
         return hipGetLastError();
     }
@@ -1106,11 +1311,26 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
         k_seam<D><<<(unsigned)b.nseamwg, SEAM_WG, 0, st>>>(b, ws);
         timer_end(timer, KIND_SEAM, st);
     }
+    if (!stats) {
+        const unsigned fgrid =
+            (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, false, false>, NT));
+        timer_begin(timer, KIND_FINAL, st);
+        k_final<D, false, false><<<fgrid, NT, 0, st>>>(b, ws, none);
+        timer_end(timer, KIND_FINAL, st);
+        return hipGetLastError();
+    }
     const unsigned fgrid =
-        (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, false>, NT));
+        (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, false, true>, NT));
     timer_begin(timer, KIND_FINAL, st);
-    k_final<D, false><<<fgrid, NT, 0, st>>>(b, ws);
+    k_final<D, false, true><<<fgrid, NT, 0, st>>>(b, ws, *stats);
     timer_end(timer, KIND_FINAL, st);
+    k_scan1<<<(unsigned)stats->nblk, SCAN_T, 0, st>>>(*stats);
+    k_scan2<<<1, SCAN_T, 0, st>>>(*stats);
+    if (stats->capacity > 0) {
+        const int64_t blocks = std::min<int64_t>((stats->capacity + 255) / 256, 4096);
+        k_stats_init<<<(unsigned)blocks, 256, 0, st>>>(*stats);
+        k_stats<D><<<(unsigned)b.ntiles, NT, 0, st>>>(b, ws, *stats);
+    }
     return hipGetLastError();
 }
 
@@ -1123,10 +1343,16 @@ hipError_t launch_index(const BatchArgs& b, hipStream_t st)
 }
 
 hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
-                        KernelTimer* timer, bool local_only)
+                        KernelTimer* timer, bool local_only, const StatsWs* stats)
 {
-    if (conn == 8) return launch_all<1>(b, ws, st, timer, local_only);
-    return launch_all<0>(b, ws, st, timer, local_only);
+    if (conn == 8) return launch_all<1>(b, ws, st, timer, local_only, stats);
+    return launch_all<0>(b, ws, st, timer, local_only, stats);
+}
+
+hipError_t launch_zero_count(int64_t* count, hipStream_t st)
+{
+    k_zero_count<<<1, 1, 0, st>>>(count);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,

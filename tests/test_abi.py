@@ -69,6 +69,30 @@ def test_validation(lib, name, args, status):
         assert len(lib.ccl_last_error()) > 0
 
 
+FAKE_CNT = 0x30000000
+FAKE_COMPS = 0x40000000
+
+
+@pytest.mark.parametrize("args,status", [
+    ((FAKE_IMG, -1, 4, 4, 8, FAKE_OUT, FAKE_COMPS, 10, FAKE_CNT), -1),  # negative height
+    ((FAKE_IMG, 4, 4, 4, 6, FAKE_OUT, FAKE_COMPS, 10, FAKE_CNT), -1),   # connectivity 6
+    ((FAKE_IMG, 4, 4, 4, 8, None, FAKE_COMPS, 10, FAKE_CNT), -1),       # null labels
+    ((FAKE_IMG, 4, 4, 4, 8, FAKE_OUT, FAKE_COMPS, 10, None), -1),       # null count
+    ((FAKE_IMG, 4, 4, 4, 8, FAKE_OUT, FAKE_COMPS, -1, FAKE_CNT), -1),   # negative capacity
+    ((FAKE_IMG, 4, 4, 4, 8, FAKE_OUT, None, 10, FAKE_CNT), -1),         # null comps
+    ((FAKE_IMG, 1 << 16, 1 << 16, 1 << 16, 8, FAKE_OUT, FAKE_COMPS, 10, FAKE_CNT), -2),
+])
+def test_stats_validation(lib, args, status):
+    f = lib.ccl_label_stats
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    lib.ccl_last_error.restype = ctypes.c_char_p
+    assert f(*args, None) == status
+    assert b"ccl_label_stats" in lib.ccl_last_error()
+
+
 def test_batch_validation(lib):
     import paper_1712_09789_amd.ccl as c  # the binding loads on CPU too
     descs = (c.ImageDesc * 3)()

@@ -1,0 +1,97 @@
+"""Per-component statistics through the C ABI (ccl_label_stats) against the
+oracle's, field by field: exact integers, so tolerance 0."""
+import numpy as np
+import pytest
+
+from oracle import oracle_label, oracle_stats
+from paper_1712_09789_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ccl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1712_09789_amd.ccl as c
+    return c
+
+
+def check(ccl, img, conn, what="", capacity=None):
+    print(f"[stats] {what} {img.shape} conn={conn} capacity={capacity}", flush=True)
+    d = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    labels, comps, count = ccl.label_stats(d, conn, capacity=capacity)
+    got = ccl.components_to_numpy(comps, count)
+    n = int(count.item())
+    want = oracle_stats(img, conn)
+    assert n == len(want), f"{what}: {n} components, oracle {len(want)}"
+    assert np.array_equal(labels.cpu().numpy(), oracle_label(img, conn))
+    k = len(got)
+    assert k == min(n, len(want) if capacity is None else capacity)
+    for f in want.dtype.names:
+        if not np.array_equal(got[f], want[f][:k]):
+            bad = np.flatnonzero(got[f] != want[f][:k])[0]
+            raise AssertionError(f"{what} conn={conn}: field {f} differs at component {bad}: "
+                                 f"got {got[bad]} want {want[bad]}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 70), (70, 1), (5, 3), (63, 65), (64, 64),
+                                 (129, 127), (300, 517)])
+@pytest.mark.parametrize("p", [0.3, 0.6])
+def test_small_and_ragged(ccl, H, W, p, conn):
+    check(ccl, wl.bernoulli(H, W, p, seed=H * 7 + W), conn, f"bernoulli{p}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("kind,kw", [("bernoulli", {"p": 0.5}), ("blobs", {"sigma": 4}),
+                                     ("checkerboard", {}), ("full", {}), ("empty", {}),
+                                     ("spiral", {}), ("serpentine", {"width": 1})])
+def test_contents_1000(ccl, kind, kw, conn):
+    check(ccl, wl.make(kind, 1000, 777, seed=1, **kw), conn, f"{kind}{kw}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_2048_bernoulli(ccl, conn):
+    check(ccl, wl.bernoulli(2048, 2048, 0.5, seed=5), conn, "C2 2048")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_4096_bench_size(ccl, conn):
+    check(ccl, wl.bernoulli(4096, 4096, 0.5, seed=0), conn, "4096")
+
+
+def test_capacity_smaller_than_count(ccl):
+    img = wl.bernoulli(300, 300, 0.4, seed=9)
+    want = oracle_stats(img, 8)
+    assert len(want) > 100
+    d = torch.from_numpy(img).cuda()
+    for cap in (0, 1, 100):
+        labels, comps, count = ccl.label_stats(d, 8, capacity=cap)
+        comps.fill_(0xAB)
+        labels, comps2, count = ccl.label_stats(d, 8, capacity=cap)
+        assert int(count.item()) == len(want)
+        got = ccl.components_to_numpy(comps2, count)
+        assert len(got) == cap
+        for f in want.dtype.names:
+            assert np.array_equal(got[f], want[f][:cap])
+    # entries past the capacity are left alone
+    labels, comps, count = ccl.label_stats(d, 8, capacity=50)
+    raw = torch.full((100 * 40,), 0xAB, dtype=torch.uint8, device="cuda")
+    lib = ccl.lib()
+    st = torch.cuda.current_stream().cuda_stream
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rc = lib.ccl_label_stats(d.data_ptr(), 300, 300, 300, 8, labels.data_ptr(), raw.data_ptr(),
+                             50, cnt.data_ptr(), st)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == len(want)
+    assert bool((raw[50 * 40:] == 0xAB).all())
+
+
+def test_empty_image_counts_zero(ccl):
+    d = torch.zeros((0, 5), dtype=torch.uint8, device="cuda")
+    labels, comps, count = ccl.label_stats(d, 8, capacity=4)
+    assert int(count.item()) == 0
