@@ -251,6 +251,64 @@ def oracle_all_cores(imgs, conn):
     return outs, time.perf_counter() - t0, cores
 
 
+def bench_stats(ccl, torch, dev, cases, devs, label_us, steps, check=True):
+    """ccl_label_stats (labels plus per-component statistics) over the
+    headline rotation, next to the plain labelling rate; the statistics of
+    the Bernoulli p = 0.5 images are compared with the oracle's, which is
+    timed on one core."""
+    size = devs[0][0].shape[0]
+    cap = ccl.max_components(size, size, 4)
+    comps = torch.empty(cap * ccl.COMPONENT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    count = torch.empty(1, dtype=torch.int64, device=dev)
+    lib = ccl.lib()
+    st = torch.cuda.current_stream()
+    sh = int(st.cuda_stream)
+    calls = [(img.data_ptr(), size, size, size, conn, out.data_ptr(), comps.data_ptr(), cap,
+              count.data_ptr(), sh) for img, out, conn in devs]
+
+    def run(k):
+        for i in range(k):
+            assert lib.ccl_label_stats(*calls[i % len(calls)]) == 0
+
+    run(len(calls))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    run(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / steps
+    ccl.timing_enable(True, kinds=["stats"])
+    run(steps)
+    kern = ccl.timing_read()
+    ccl.timing_enable(False)
+    ms, n = kern["stats"]
+    out = {"Gpx/s": round(size * size / us / 1e3, 1), "us_per_step": round(us, 2),
+           "stats_kernels_us": round(1e3 * ms / max(n, 1), 2),
+           "label_only_us": round(label_us, 2), "overhead": round(us / label_us, 3)}
+    if check:
+        import oracle
+        exact, cpu_secs, px = True, 0.0, 0
+        for i, (name, img, conn) in enumerate(cases):
+            if not name.startswith("bernoulli{'p': 0.5}"):
+                continue
+            assert lib.ccl_label_stats(*calls[i]) == 0
+            got = ccl.components_to_numpy(comps, count)
+            c0 = time.perf_counter()
+            want = oracle.oracle_stats(img, conn)
+            cpu_secs += time.perf_counter() - c0
+            px += img.size
+            exact &= len(got) == len(want) and all(np.array_equal(got[f], want[f])
+                                                   for f in want.dtype.names)
+        out["exact_sampled"] = bool(exact)
+        out["cpu_baseline"] = {"value": round(px / cpu_secs / 1e9, 5), "unit": "Gpixel/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "the two Bernoulli p = 0.5 images (4- and 8-connected) once"}
+    del comps
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(ccl, torch, dev, check=True, n=256, reps=5):
     """256 uint8 images, sides log-uniform in [64, 2048], half Bernoulli and
     half blobs at random density, 8-connectivity: one ccl_label_batch call
@@ -374,6 +432,9 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--profile-stats", type=int, default=0, metavar="ROUNDS",
+                    help="only run ccl_label_stats over the headline images ROUNDS times "
+                         "(for a kernel trace of the statistics path) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel over MIB MiB (counter calibration)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"),
@@ -431,6 +492,20 @@ def main():
         devs.append((torch.from_numpy(img).to(dev), torch.empty((size, size), dtype=torch.int32,
                                                               device=dev), conn))
     torch.cuda.synchronize()
+
+    if args.profile_stats:
+        cap = ccl.max_components(size, size, 4)
+        comps = torch.empty(cap * ccl.COMPONENT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        count = torch.empty(1, dtype=torch.int64, device=dev)
+        sh = int(torch.cuda.current_stream().cuda_stream)
+        for _ in range(args.profile_stats):
+            for img, out, conn in devs:
+                assert ccl.lib().ccl_label_stats(img.data_ptr(), size, size, size, conn,
+                                                 out.data_ptr(), comps.data_ptr(), cap,
+                                                 count.data_ptr(), sh) == 0
+        torch.cuda.synchronize()
+        log(f"[bench] profile-stats: {args.profile_stats} rounds of {len(devs)} images")
+        return
 
     # exactness: one labelling of every case, compared with the CPU checker,
     # which is timed on this host's core as the baseline
@@ -534,6 +609,9 @@ def main():
         log(f"[bench] 8192^2: {extra}")
 
     if not args.no_extra:
+        result["stats_4096"] = bench_stats(ccl, torch, dev, cases, devs, 1e3 * ms_step,
+                                           min(args.steps, 140), check=cpu is not None)
+        log(f"[bench] stats: {result['stats_4096']}")
         result["batch_256"] = bench_batch(ccl, torch, dev, check=cpu is not None)
         log(f"[bench] batch: {result['batch_256']}")
         result["serving"] = bench_serving(torch, dev)

@@ -282,7 +282,8 @@ static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, boo
     if (rc != CCL_OK) return rc;
     const int64_t label_bytes = align256(L.bytes());
     void* base = nullptr;
-    rc = get_workspace(label_bytes + (so ? stats_workspace_bytes(L.ntiles) : 0), st, &base);
+    rc = get_workspace(label_bytes + (so ? stats_workspace_bytes(L.ntiles, imgs[0].ntx, imgs[0].nty) : 0),
+                       st, &base);
     if (rc != CCL_OK) return rc;
     BatchArgs b;
     Workspace ws;
@@ -290,7 +291,7 @@ static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, boo
     if (rc != CCL_OK) return rc;
     StatsWs sw{};
     if (so) {
-        sw = carve_stats(static_cast<char*>(base) + label_bytes, L.ntiles);
+        sw = carve_stats(static_cast<char*>(base) + label_bytes, L.ntiles, imgs[0].ntx, imgs[0].nty);
         sw.comps = reinterpret_cast<CompStats*>(so->comps);
         sw.capacity = so->capacity;
         sw.count = so->count;

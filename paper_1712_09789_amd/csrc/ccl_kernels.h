@@ -91,31 +91,52 @@ struct CompStats {
 // the scanned count of its segment plus the smallest pixels left of it there.
 constexpr int SCAN_T = 1024;                // scan workgroup size
 constexpr int SCAN_BLK = 4 * SCAN_T;        // segments per first-level scan block
+// Partial statistics of one component over part of the image, in global
+// coordinates.
+struct StatRec {
+    int32_t num;  // component number
+    int32_t area, x_min, x_max, y_min, y_max;
+    int64_t sum_x, sum_y;
+};
+constexpr int MERGE_FAN = 4;     // a merge workgroup takes 4 x 4 parts of the level below
+constexpr int MERGE_HT = 2048;   // its hash table: distinct components, and records out
+
 struct StatsWs {
     uint64_t* rootbits;  // [ntiles][TILE_ROWS] smallest pixels of components, by tile row
     uint32_t* seg;       // [ntiles * TILE_ROWS] per segment: count, then exclusive scan in its block
     uint32_t* bsum;      // [nblk] segments' total per scan block
     uint32_t* boff;      // [nblk] exclusive scan of bsum
+    StatRec* rec0;       // [ntiles][NSLOTS] per tile: partials of its border components
+    uint32_t* cnt0;      // [ntiles]
+    StatRec* rec1;       // [ngroups1][MERGE_HT] per 4 x 4 tiles: merged partials
+    uint32_t* cnt1;      // [ngroups1]
     int64_t nseg, nblk;
+    int32_t g1x, g1y;    // grid of first-level merge groups
     CompStats* comps;    // caller's output [capacity]
     int64_t capacity;
     int64_t* count;      // caller's output: number of components
 };
 
-inline int64_t stats_workspace_bytes(int64_t ntiles)
+inline int64_t stats_workspace_bytes(int64_t ntiles, int ntx, int nty)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     const int64_t nseg = ntiles * TILE_ROWS, nblk = (nseg + SCAN_BLK - 1) / SCAN_BLK;
-    return up(nseg * 8) + up(nseg * 4) + 2 * up(nblk * 4);
+    const int64_t ng1 = (int64_t)((ntx + MERGE_FAN - 1) / MERGE_FAN) * ((nty + MERGE_FAN - 1) / MERGE_FAN);
+    return up(nseg * 8) + up(nseg * 4) + 2 * up(nblk * 4) +
+           up(ntiles * NSLOTS * (int64_t)sizeof(StatRec)) + up(ntiles * 4) +
+           up(ng1 * MERGE_HT * (int64_t)sizeof(StatRec)) + up(ng1 * 4);
 }
 
-inline StatsWs carve_stats(void* base, int64_t ntiles)
+inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     char* p = static_cast<char*>(base);
     StatsWs s{};
     s.nseg = ntiles * TILE_ROWS;
     s.nblk = (s.nseg + SCAN_BLK - 1) / SCAN_BLK;
+    s.g1x = (ntx + MERGE_FAN - 1) / MERGE_FAN;
+    s.g1y = (nty + MERGE_FAN - 1) / MERGE_FAN;
+    const int64_t ng1 = (int64_t)s.g1x * s.g1y;
     s.rootbits = reinterpret_cast<uint64_t*>(p);
     p += up(s.nseg * 8);
     s.seg = reinterpret_cast<uint32_t*>(p);
@@ -123,10 +144,21 @@ inline StatsWs carve_stats(void* base, int64_t ntiles)
     s.bsum = reinterpret_cast<uint32_t*>(p);
     p += up(s.nblk * 4);
     s.boff = reinterpret_cast<uint32_t*>(p);
+    p += up(s.nblk * 4);
+    s.rec0 = reinterpret_cast<StatRec*>(p);
+    p += up(ntiles * NSLOTS * (int64_t)sizeof(StatRec));
+    s.cnt0 = reinterpret_cast<uint32_t*>(p);
+    p += up(ntiles * 4);
+    s.rec1 = reinterpret_cast<StatRec*>(p);
+    p += up(ng1 * MERGE_HT * (int64_t)sizeof(StatRec));
+    s.cnt1 = reinterpret_cast<uint32_t*>(p);
     return s;
 }
 
-enum { KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, KIND_BLOCK = 4, NKINDS = 5 };
+enum {
+    KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, KIND_BLOCK = 4,
+    KIND_STATS = 5, NKINDS = 6
+};
 
 struct KernelTimer;  // host-side event recorder, null when timing is off
 void timer_begin(KernelTimer* t, int kind, hipStream_t st);

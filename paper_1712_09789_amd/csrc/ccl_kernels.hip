@@ -1154,14 +1154,56 @@ __device__ __forceinline__ uint32_t bit_position_sum(uint64_t m)
 template <int D>
 struct StatsShared : Lines<D> {
     uint16_t RL[Geo<D>::MAXR];
+    alignas(16) uint16_t ent[RUNTAB_PER_TILE];  // the tile's run table
+    // border components of the tile, accumulated by representative slot
+    // (tile-local coordinates)
+    int32_t area[NSLOTS], xmin[NSLOTS], xmax[NSLOTS], ymin[NSLOTS], ymax[NSLOTS];
+    uint32_t sx[NSLOTS], sy[NSLOTS];
+    int32_t lab[NSLOTS];
+    // interior components, accumulated at the run holding their smallest pixel
+    int32_t iarea[Geo<D>::MAXR], ixmin[Geo<D>::MAXR], ixmax[Geo<D>::MAXR], iymax[Geo<D>::MAXR];
+    uint32_t isx[Geo<D>::MAXR], isy[Geo<D>::MAXR];
+    uint8_t iroot[Geo<D>::MAXR];
+    uint32_t nrec;
 };
 
-// Statistics of every run of a tile, added to its component's entry.  The
-// run's label is read back from the label map at its smallest pixel; the
-// component's number is the scanned count of its smallest pixel's segment
-// plus the smallest pixels left of it in that segment.
+// Adds a partial record (global coordinates) to a component's entry.
+__device__ __forceinline__ void add_stats(CompStats* c, int area, int xmin, int xmax, int ymax,
+                                          uint64_t sx, uint64_t sy)
+{
+    atomicAdd(&c->area, area);
+    atomicMin(&c->x_min, xmin);
+    atomicMax(&c->x_max, xmax);
+    atomicMax(&c->y_max, ymax);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&c->sum_x), (unsigned long long)sx);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&c->sum_y), (unsigned long long)sy);
+}
+
+// Number of the component with label L: scanned count of its smallest
+// pixel's segment plus the smallest pixels left of it in that segment.
+__device__ __forceinline__ int64_t component_number(const ImageArgs& a, const StatsWs& st,
+                                                    int32_t L)
+{
+    uint32_t ry, rx;
+    divmod_w((uint32_t)L - 1u, (uint32_t)a.W, a.wmagic, ry, rx);
+    const int64_t sg = (int64_t)ry * a.ntx + rx / TW;
+    const int64_t rt = ((int64_t)(ry / TILE_ROWS) * a.ntx + rx / TW) * TILE_ROWS + ry % TILE_ROWS;
+    return (int64_t)st.seg[sg] + st.boff[sg / SCAN_BLK] +
+           popc64(st.rootbits[rt] & ((1ull << (rx % TW)) - 1ull));
+}
+
+// Statistics of every run of a tile.  A run's label is read back from the
+// label map at its smallest pixel.  Runs of interior components (wholly in
+// this tile) are summed in LDS at the run holding the component's smallest
+// pixel, which then writes the whole entry; runs of border components are
+// summed per component in LDS and leave the tile as one partial record each,
+// which two merge levels combine before they reach the entries, so that a
+// component spanning the image is not updated once per tile.  The run
+// holding a border component's smallest pixel writes its label and top row.
+constexpr int ST = 1024;  // k_stats threads per tile: latency of the per-run loads is hidden
+                          // inside the workgroup (its LDS allows two per compute unit)
 template <int D>
-__global__ __launch_bounds__(NT) void k_stats(BatchArgs b, Workspace ws, StatsWs st)
+__global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs st)
 {
     __shared__ StatsShared<D> sh;
     const int tid = threadIdx.x;
@@ -1172,22 +1214,38 @@ __global__ __launch_bounds__(NT) void k_stats(BatchArgs b, Workspace ws, StatsWs
     const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
     if (tid < TILE_ROWS) sh.M[tid] = ws.bits[T * TILE_ROWS + tid];
+    if (tid < NSLOTS) {
+        sh.area[tid] = 0;
+        sh.xmin[tid] = sh.ymin[tid] = INT32_MAX;
+        sh.xmax[tid] = sh.ymax[tid] = -1;
+        sh.sx[tid] = sh.sy[tid] = 0u;
+    }
+    if (tid == 0) sh.nrec = 0u;
     __syncthreads();
     build_lines<D>(sh, tid);
-    list_runs<D>(sh, sh.RL, tid);
-    __syncthreads();
+    if (tid < NT) list_runs<D>(sh, sh.RL, tid);
     const uint32_t R = sh.base[Geo<D>::NL];
-    for (uint32_t id = tid; id < R; id += NT) {
+    if (tid < NT && 8u * tid < R)
+        reinterpret_cast<uint4*>(sh.ent)[tid] =
+            reinterpret_cast<const uint4*>(ws.runtab + T * RUNTAB_PER_TILE)[tid];
+    for (uint32_t id = tid; id < R; id += ST) {
+        sh.iarea[id] = 0;
+        sh.ixmin[id] = INT32_MAX;
+        sh.ixmax[id] = sh.iymax[id] = -1;
+        sh.isx[id] = sh.isy[id] = 0u;
+        sh.iroot[id] = 0;
+    }
+    __syncthreads();
+    for (uint32_t id = tid; id < R; id += ST) {
         const uint32_t rec = sh.RL[id];
         const int s0 = rec & 63, l = rec >> 6;
         const int e = s0 + ctz64_or64(~(sh.LM[l] >> s0)) - 1;
-        uint32_t area, ymin, ymax, key;
-        uint64_t sx, sy;
+        uint32_t area, ymin, ymax, key, sx, sy;
         if (!D) {
             area = (uint32_t)(e - s0 + 1);
             ymin = ymax = (uint32_t)l;
-            sx = (uint64_t)(s0 + e) * area / 2;
-            sy = (uint64_t)l * area;
+            sx = (uint32_t)(s0 + e) * area / 2u;
+            sy = (uint32_t)l * area;
             key = (uint32_t)(l * TW + s0);
         } else {
             const uint64_t span = span_mask(s0, e);
@@ -1196,32 +1254,186 @@ __global__ __launch_bounds__(NT) void k_stats(BatchArgs b, Workspace ws, StatsWs
             area = at + ab;
             ymin = top ? 2u * l : 2u * l + 1u;
             ymax = bot ? 2u * l + 1u : 2u * l;
-            sx = (uint64_t)bit_position_sum(top) + bit_position_sum(bot);
-            sy = (uint64_t)(2 * l) * at + (uint64_t)(2 * l + 1) * ab;
+            sx = bit_position_sum(top) + bit_position_sum(bot);
+            sy = (uint32_t)(2 * l) * at + (uint32_t)(2 * l + 1) * ab;
             key = top ? (uint32_t)(2 * l * TW + ctz64(top)) : (uint32_t)((2 * l + 1) * TW + s0);
         }
         const int64_t kpos = (int64_t)(gy0 + (int)(key / TW)) * a.W + gx0 + (int)(key % TW);
         const int32_t L = a.labels[kpos];
         if (L <= 0 || (int64_t)L > kpos + 1) continue;  // not a label of this pixel
-        uint32_t ry, rx;
-        divmod_w((uint32_t)L - 1u, (uint32_t)a.W, a.wmagic, ry, rx);
-        const int64_t sg = (int64_t)ry * a.ntx + rx / TW;
-        const int64_t rt = ((int64_t)(ry / TILE_ROWS) * a.ntx + rx / TW) * TILE_ROWS + ry % TILE_ROWS;
-        const int64_t num = (int64_t)st.seg[sg] + st.boff[sg / SCAN_BLK] +
-                            popc64(st.rootbits[rt] & ((1ull << (rx % TW)) - 1ull));
+        const bool is_root = kpos == (int64_t)L - 1;
+        const uint32_t en = sh.ent[id];
+        const bool border = (en & RT_BORDER) != 0;
+        if (!border) {
+            // the run holding the smallest pixel (tile position = the entry)
+            const int ky = (int)(en / TW), kx = (int)(en % TW);
+            const int rl = D ? ky >> 1 : ky;
+            const uint32_t rr = sh.base[rl] + popc64(sh.LS[rl] & upto(kx)) - 1u;
+            atomicAdd(&sh.iarea[rr], (int)area);
+            atomicMin(&sh.ixmin[rr], s0);
+            atomicMax(&sh.ixmax[rr], e);
+            atomicMax(&sh.iymax[rr], (int)ymax);
+            atomicAdd(&sh.isx[rr], sx);
+            atomicAdd(&sh.isy[rr], sy);
+            if (is_root) sh.iroot[id] = 1;
+            continue;
+        }
+        {
+            const int rep = en & 0x7fff;
+            atomicAdd(&sh.area[rep], (int)area);
+            atomicMin(&sh.xmin[rep], s0);
+            atomicMax(&sh.xmax[rep], e);
+            atomicMin(&sh.ymin[rep], (int)ymin);
+            atomicMax(&sh.ymax[rep], (int)ymax);
+            atomicAdd(&sh.sx[rep], sx);
+            atomicAdd(&sh.sy[rep], sy);
+            sh.lab[rep] = L;
+            if (!is_root) continue;  // only the label remains to write
+        }
+        const int64_t num = component_number(a, st, L);
         if (num >= st.capacity) continue;
         CompStats* c = st.comps + num;
-        atomicAdd(&c->area, (int)area);
-        atomicMin(&c->x_min, gx0 + s0);
-        atomicMin(&c->y_min, gy0 + (int)ymin);
-        atomicMax(&c->x_max, gx0 + e);
-        atomicMax(&c->y_max, gy0 + (int)ymax);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&c->sum_x),
-                  (unsigned long long)(sx + (uint64_t)area * gx0));
-        atomicAdd(reinterpret_cast<unsigned long long*>(&c->sum_y),
-                  (unsigned long long)(sy + (uint64_t)area * gy0));
-        // the run that holds the component's smallest pixel writes the label
-        if (kpos == (int64_t)L - 1) c->label = L;
+        c->label = L;
+        c->y_min = (int32_t)(kpos / a.W);
+    }
+    __syncthreads();
+    // interior components: the whole entry from the run holding the smallest pixel
+    for (uint32_t id = tid; id < R; id += ST) {
+        if (!sh.iroot[id]) continue;
+        const uint32_t rec = sh.RL[id];
+        const int s0 = rec & 63, l = rec >> 6;
+        // smallest pixel: the run's first foreground pixel in raster order
+        int ky = l, kx = s0;
+        if (D) {
+            const int e = s0 + ctz64_or64(~(sh.LM[l] >> s0)) - 1;
+            const uint64_t top = sh.M[2 * l] & span_mask(s0, e);
+            ky = top ? 2 * l : 2 * l + 1;
+            kx = top ? ctz64(top) : s0;
+        }
+        const int64_t kpos = (int64_t)(gy0 + ky) * a.W + gx0 + kx;
+        const int32_t L = (int32_t)(kpos + 1);
+        const int64_t num = component_number(a, st, L);
+        if (num >= st.capacity) continue;
+        const int area = sh.iarea[id];
+        CompStats c;
+        c.label = L;
+        c.area = area;
+        c.x_min = gx0 + sh.ixmin[id];
+        c.y_min = gy0 + ky;
+        c.x_max = gx0 + sh.ixmax[id];
+        c.y_max = gy0 + sh.iymax[id];
+        c.sum_x = (int64_t)(sh.isx[id] + (uint64_t)area * gx0);
+        c.sum_y = (int64_t)(sh.isy[id] + (uint64_t)area * gy0);
+        st.comps[num] = c;
+    }
+    // one partial record per border component of the tile
+    const int area = tid < NSLOTS ? sh.area[tid] : 0;
+    if (area > 0) {
+        const int64_t num = component_number(a, st, sh.lab[tid]);
+        if (num < st.capacity) {
+            StatRec r;
+            r.num = (int32_t)num;
+            r.area = area;
+            r.x_min = gx0 + sh.xmin[tid];
+            r.x_max = gx0 + sh.xmax[tid];
+            r.y_min = gy0 + sh.ymin[tid];
+            r.y_max = gy0 + sh.ymax[tid];
+            r.sum_x = (int64_t)(sh.sx[tid] + (uint64_t)area * gx0);
+            r.sum_y = (int64_t)(sh.sy[tid] + (uint64_t)area * gy0);
+            st.rec0[T * NSLOTS + atomicAdd(&sh.nrec, 1u)] = r;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) st.cnt0[T] = sh.nrec;
+}
+
+// One merge level: workgroup (I, J) combines the records of parts
+// (4I .. 4I+3, 4J .. 4J+3) of the level below (each `part_px` pixels square)
+// in an LDS hash table keyed by component number.  A combined record whose
+// box stays off the inner edges of the workgroup's region describes a whole
+// component (it cannot reach outside without crossing them) and goes to the
+// component's entry; the others are written out for the next level (FINAL =
+// false) or also go to the entries (FINAL).  Records that find the table
+// full go straight to the entries (atomics commute).
+constexpr int MERGE_T = 1024;
+template <bool FINAL>
+__global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatRec* in,
+                                                          const uint32_t* in_cnt, int in_cap,
+                                                          int inx, int iny, int part_px, int W,
+                                                          int H, StatRec* out, uint32_t* out_cnt,
+                                                          int outx)
+{
+    __shared__ int32_t hkey[MERGE_HT], harea[MERGE_HT], hxmin[MERGE_HT], hxmax[MERGE_HT],
+        hymin[MERGE_HT], hymax[MERGE_HT];
+    __shared__ unsigned long long hsx[MERGE_HT], hsy[MERGE_HT];
+    __shared__ uint32_t nout;
+    const int tid = threadIdx.x;
+    for (int h = tid; h < MERGE_HT; h += MERGE_T) {
+        hkey[h] = -1;
+        harea[h] = 0;
+        hxmin[h] = hymin[h] = INT32_MAX;
+        hxmax[h] = hymax[h] = -1;
+        hsx[h] = hsy[h] = 0ull;
+    }
+    if (tid == 0) nout = 0u;
+    __syncthreads();
+    const int I = (int)(blockIdx.x % (unsigned)outx), J = (int)(blockIdx.x / (unsigned)outx);
+    for (int part = 0; part < MERGE_FAN * MERGE_FAN; ++part) {
+        const int i = I * MERGE_FAN + part % MERGE_FAN, j = J * MERGE_FAN + part / MERGE_FAN;
+        if (i >= inx || j >= iny) continue;
+        const int64_t sg = (int64_t)j * inx + i;
+        const uint32_t n = in_cnt[sg];
+        for (uint32_t k = tid; k < n; k += MERGE_T) {
+            const StatRec r = in[sg * in_cap + k];
+            uint32_t h = ((uint32_t)r.num * 0x9E3779B1u) >> (32 - 11);
+            static_assert(MERGE_HT == 1 << 11, "hash width");
+            bool placed = false;
+            for (int probe = 0; probe < 64 && !placed; ++probe, h = (h + 1u) & (MERGE_HT - 1)) {
+                const int32_t old = atomicCAS(&hkey[h], -1, r.num);
+                if (old == -1 || old == r.num) {
+                    atomicAdd(&harea[h], r.area);
+                    atomicMin(&hxmin[h], r.x_min);
+                    atomicMax(&hxmax[h], r.x_max);
+                    atomicMin(&hymin[h], r.y_min);
+                    atomicMax(&hymax[h], r.y_max);
+                    atomicAdd(&hsx[h], (unsigned long long)r.sum_x);
+                    atomicAdd(&hsy[h], (unsigned long long)r.sum_y);
+                    placed = true;
+                }
+            }
+            if (!placed)
+                add_stats(st.comps + r.num, r.area, r.x_min, r.x_max, r.y_max,
+                          (uint64_t)r.sum_x, (uint64_t)r.sum_y);
+        }
+    }
+    __syncthreads();
+    // the region's inner edges (image edges do not count)
+    const int span = part_px * MERGE_FAN;
+    const int x0 = I * span, y0 = J * span;
+    const int x1 = min(x0 + span, W) - 1, y1 = min(y0 + span, H) - 1;
+    for (int h = tid; h < MERGE_HT; h += MERGE_T) {
+        const int32_t num = hkey[h];
+        if (num < 0) continue;
+        const bool crosses = (hxmin[h] == x0 && x0 > 0) || (hxmax[h] == x1 && x1 < W - 1) ||
+                             (hymin[h] == y0 && y0 > 0) || (hymax[h] == y1 && y1 < H - 1);
+        if (FINAL || !crosses) {
+            add_stats(st.comps + num, harea[h], hxmin[h], hxmax[h], hymax[h], hsx[h], hsy[h]);
+        } else {
+            StatRec r;
+            r.num = num;
+            r.area = harea[h];
+            r.x_min = hxmin[h];
+            r.x_max = hxmax[h];
+            r.y_min = hymin[h];
+            r.y_max = hymax[h];
+            r.sum_x = (int64_t)hsx[h];
+            r.sum_y = (int64_t)hsy[h];
+            out[(int64_t)blockIdx.x * MERGE_HT + atomicAdd(&nout, 1u)] = r;
+        }
+    }
+    if (!FINAL) {
+        __syncthreads();
+        if (tid == 0) out_cnt[blockIdx.x] = nout;
     }
 }
 
@@ -1324,13 +1536,25 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
     timer_begin(timer, KIND_FINAL, st);
     k_final<D, false, true><<<fgrid, NT, 0, st>>>(b, ws, *stats);
     timer_end(timer, KIND_FINAL, st);
+    timer_begin(timer, KIND_STATS, st);
     k_scan1<<<(unsigned)stats->nblk, SCAN_T, 0, st>>>(*stats);
     k_scan2<<<1, SCAN_T, 0, st>>>(*stats);
     if (stats->capacity > 0) {
         const int64_t blocks = std::min<int64_t>((stats->capacity + 255) / 256, 4096);
         k_stats_init<<<(unsigned)blocks, 256, 0, st>>>(*stats);
-        k_stats<D><<<(unsigned)b.ntiles, NT, 0, st>>>(b, ws, *stats);
+        k_stats<D><<<(unsigned)b.ntiles, ST, 0, st>>>(b, ws, *stats);
+        static_assert(TW == TILE_ROWS, "square tiles: merge regions are squares of tiles");
+        const ImageArgs& a = b.one;
+        const int g2x = (stats->g1x + MERGE_FAN - 1) / MERGE_FAN;
+        const int g2y = (stats->g1y + MERGE_FAN - 1) / MERGE_FAN;
+        k_stats_merge<false><<<(unsigned)(stats->g1x * stats->g1y), MERGE_T, 0, st>>>(
+            *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, TW, a.W, a.H, stats->rec1,
+            stats->cnt1, stats->g1x);
+        k_stats_merge<true><<<(unsigned)(g2x * g2y), MERGE_T, 0, st>>>(
+            *stats, stats->rec1, stats->cnt1, MERGE_HT, stats->g1x, stats->g1y, TW * MERGE_FAN,
+            a.W, a.H, nullptr, nullptr, g2x);
     }
+    timer_end(timer, KIND_STATS, st);
     return hipGetLastError();
 }
 
