@@ -140,6 +140,29 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
                     int64_t capacity, int64_t* count, void* stream);
 
 /*
+ * The paper's ablation of its local step (Section 4, effectiveness of coarse
+ * labelling), for study rather than speed: the local step is rerun with the
+ * coarse labelling along rows and columns (CCL_C2FL, the method), along rows
+ * only (CCL_RC2FL), along columns only (CCL_CC2FL) or not at all
+ * (CCL_NC2FL), followed by the usual block merge and final update.  Row
+ * connection makes each row run one union-find node (without it every
+ * foreground pixel is a node); column connection starts each node linked to
+ * the node above it.  4-connectivity (the paper's setting).
+ *   variant   CCL_C2FL .. CCL_NC2FL.
+ *   labels    as in ccl_label: identical for every variant.
+ *   counters  NULL, or a device uint32 array of 2 * tile count entries
+ *             (tiles in row-major order, ccl_tile_cols() x ccl_tile_rows()
+ *             pixels each): per tile, the number of find-loop steps (the
+ *             paper's iterations) and of atomic merge attempts in the local
+ *             step.
+ * Other arguments and errors as ccl_label; CCL_ERR_INVALID_ARG for an
+ * unknown variant.
+ */
+enum { CCL_C2FL = 0, CCL_RC2FL = 1, CCL_CC2FL = 2, CCL_NC2FL = 3 };
+int ccl_label_ablation(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                       int32_t variant, int32_t* labels, uint32_t* counters, void* stream);
+
+/*
  * Debugging aid for the local step alone (Section 3.1): every tile is
  * labelled as if it were a separate image, and each foreground pixel gets
  * 1 + the raster position (in the whole image) of the smallest pixel of its

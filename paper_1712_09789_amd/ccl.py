@@ -27,6 +27,8 @@ COMPONENT_DTYPE = np.dtype([("label", np.int32), ("area", np.int32),
                             ("x_max", np.int32), ("y_max", np.int32),
                             ("sum_x", np.int64), ("sum_y", np.int64)])
 assert COMPONENT_DTYPE.itemsize == 40
+# Variants of ccl_label_ablation (the paper's C2FL, RC2FL, CC2FL, NC2FL).
+ABLATIONS = {"C2FL": 0, "RC2FL": 1, "CC2FL": 2, "NC2FL": 3}
 
 
 class CCLError(RuntimeError):
@@ -53,6 +55,8 @@ def _load() -> ctypes.CDLL:
         f.argtypes = [vp, i32, i32, i64, i32, vp, vp]
     lib.ccl_label_stats.restype = ctypes.c_int
     lib.ccl_label_stats.argtypes = [vp, i32, i32, i64, i32, vp, vp, i64, vp, vp]
+    lib.ccl_label_ablation.restype = ctypes.c_int
+    lib.ccl_label_ablation.argtypes = [vp, i32, i32, i64, i32, vp, vp, vp]
     lib.ccl_label_batch.restype = ctypes.c_int
     lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), i32, vp]
     lib.ccl_tile_cols.restype = i32
@@ -165,6 +169,25 @@ def components_to_numpy(comps: torch.Tensor, count: torch.Tensor) -> np.ndarray:
     n = min(int(count.item()), comps.numel() // COMPONENT_DTYPE.itemsize)
     raw = comps[:n * COMPONENT_DTYPE.itemsize].cpu().numpy()
     return raw.view(COMPONENT_DTYPE).copy()
+
+
+def label_ablation(img: torch.Tensor, variant: str = "C2FL", out: torch.Tensor | None = None,
+                   counters: bool = False, stream=None):
+    """4-connected labels through one of the paper's local-step variants
+    (ccl_label_ablation).  With counters=True also returns a (tiles, 2) int32
+    device tensor of per-tile find-loop steps and atomic merge attempts
+    (tiles in row-major order; the C side writes them as uint32)."""
+    H, W, pitch = _image_args(img)
+    out = _out_for(img, out)
+    cnt = None
+    if counters:
+        tc, tr = tile_shape()
+        ntiles = ((W + tc - 1) // tc) * ((H + tr - 1) // tr)
+        cnt = torch.zeros((max(ntiles, 1), 2), dtype=torch.int32, device=img.device)
+    _check(_lib.ccl_label_ablation(img.data_ptr(), H, W, pitch, ABLATIONS[variant],
+                                   out.data_ptr(), cnt.data_ptr() if cnt is not None else None,
+                                   _stream_handle(stream)))
+    return (out, cnt) if counters else out
 
 
 def label_local(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | None = None,

@@ -274,7 +274,8 @@ struct StatsOut {
 };
 
 static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, bool local_only,
-                     const char* who, const StatsOut* so = nullptr)
+                     const char* who, const StatsOut* so = nullptr, int ablation = -1,
+                     uint32_t* counters = nullptr)
 {
     if (imgs.empty()) return CCL_OK;
     ClassLayout L;
@@ -297,7 +298,9 @@ static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, boo
         sw.count = so->count;
     }
     hipError_t e = launch_index(b, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && ablation >= 0)
+        e = launch_ablation(b, ws, st, ablation, counters);
+    else if (e == hipSuccess)
         e = launch_label(b, conn, ws, st, active_timer(), local_only, so ? &sw : nullptr);
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
     return CCL_OK;
@@ -365,6 +368,20 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
     std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, connectivity, labels));
     StatsOut so{comps, capacity, count};
     return run_batch(one, connectivity, st, false, who, &so);
+}
+
+int ccl_label_ablation(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                       int32_t variant, int32_t* labels, uint32_t* counters, void* stream)
+{
+    g_err.clear();
+    const char* who = "ccl_label_ablation";
+    if (variant < CCL_C2FL || variant > CCL_NC2FL)
+        return fail(CCL_ERR_INVALID_ARG, "%s: variant %d is not one of 0..3", who, variant);
+    int rc = validate(img, H, W, pitch_bytes, 4, labels, who);
+    if (rc != CCL_OK || H == 0 || W == 0) return rc;
+    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, 4, labels));
+    return run_batch(one, 4, static_cast<hipStream_t>(stream), false, who, nullptr, variant,
+                     counters);
 }
 
 int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,

@@ -176,6 +176,11 @@ hipError_t launch_index(const BatchArgs& b, hipStream_t st);
 // pixels of components, and the statistics kernels follow it.
 hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
                         KernelTimer* timer, bool local_only, const StatsWs* stats = nullptr);
+// The local step's ablation variants (0 = rows and columns, 1 = rows only,
+// 2 = columns only, 3 = none), 4-connectivity, a single image, followed by
+// the usual merge and final kernels; `counters` (2 per tile) may be null.
+hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t st, int variant,
+                           uint32_t* counters);
 // Writes *count = 0 (an empty image has no components).
 hipError_t launch_zero_count(int64_t* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,

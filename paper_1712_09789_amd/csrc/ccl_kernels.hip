@@ -121,6 +121,38 @@ __device__ uint32_t pfind(uint32_t* P, uint32_t x)
     return v;
 }
 
+// Counting versions for the ablation study: `it` counts steps of the find
+// loops (the paper's iterations), `at` the atomic merge attempts.
+__device__ uint32_t pfind_count(uint32_t* P, uint32_t x, uint32_t& it)
+{
+    uint32_t v = lds_ld(P + x);
+    while (pk_id(v) != x) {
+        ++it;
+        const uint32_t p = pk_id(v);
+        const uint32_t w = lds_ld(P + p);
+        if (pk_id(w) == p) return w;
+        __hip_atomic_fetch_min(P + x, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = pk_id(w);
+        v = lds_ld(P + x);
+    }
+    return v;
+}
+
+__device__ void punion_count(uint32_t* P, uint32_t a, uint32_t b, uint32_t& it, uint32_t& at)
+{
+    while (true) {
+        uint32_t ra = pfind_count(P, a, it), rb = pfind_count(P, b, it);
+        if (ra == rb) return;
+        if (ra < rb) { uint32_t t = ra; ra = rb; rb = t; }
+        ++at;
+        const uint32_t old = __hip_atomic_fetch_min(P + pk_id(ra), rb, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == ra) return;
+        a = pk_id(old);
+        b = pk_id(rb);
+    }
+}
+
 // The paper's merge (Section 3.1.3): compare the two roots and point the one
 // with the larger key at the other, atomically; if it stopped being a root
 // in the meantime, continue with the parent it had.
@@ -1440,6 +1472,212 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
 __global__ void k_zero_count(int64_t* count) { *count = 0; }
 
 // ---------------------------------------------------------------------------
+// ablations of the local step (4-connectivity, the paper's setting)
+// ---------------------------------------------------------------------------
+
+// The paper's revisions of its local step (Section 4): coarse labelling along
+// rows and columns (C2FL, the method), along rows only (RC2FL), along
+// columns only (CC2FL), or none (NC2FL).  Row connection = a row's run of
+// foreground pixels is one node; without it every foreground pixel is its
+// own node.  Column connection = each node starts linked to the node holding
+// the leftmost foreground pixel above it; without it every node starts as
+// its own root.  Refinement then merges every adjacency the coarse structure
+// does not already hold.  The products are those of k_local (the run table
+// indexed by row runs), so the merge and final kernels run unchanged; with a
+// counter array each tile also reports its find-loop steps and atomic merge
+// attempts.  One 256-thread workgroup per tile.
+enum { ABL_ROW = 1, ABL_COL = 2 };
+constexpr int ABL_MAXN = TILE_ROWS * TW;          // nodes per tile, at most (pixels)
+constexpr int ABL_MAXE = 2 * TILE_ROWS * TW;      // refinement edges, at most
+
+struct AblationShared : Lines<0> {
+    uint64_t NS[TILE_ROWS];       // node starts of each row
+    uint32_t nbase[TILE_ROWS + 1];  // id of the first node of each row
+    uint32_t P[ABL_MAXN];
+    uint16_t NL[ABL_MAXN];        // node record: start column | row << 6
+    uint32_t EL[ABL_MAXE];
+    uint32_t nedges, cit, cat;
+};
+
+// Node of row l holding foreground column x.
+__device__ __forceinline__ uint32_t abl_node(const AblationShared& sh, int l, int x)
+{
+    return sh.nbase[l] + popc64(sh.NS[l] & upto(x)) - 1u;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_local_ablate(BatchArgs b, Workspace ws, uint32_t* counters)
+{
+    constexpr bool ROW = MODE & ABL_ROW, COL = MODE & ABL_COL;
+    __shared__ AblationShared sh;
+    const int tid = threadIdx.x;
+    const int64_t T = blockIdx.x;
+    const ImageArgs a = b.one;
+    const int t = (int)T;
+    const int tx = t % a.ntx, ty = t / a.ntx;
+    const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
+
+    // initialisation: the tile's foreground bits
+    const uint32_t m16 = chunk_mask(fetch_chunk(a, t, tid));
+    uint16_t* h = reinterpret_cast<uint16_t*>(sh.M);
+    h[tid] = (uint16_t)m16;
+    if (tid == 0) sh.nedges = sh.cit = sh.cat = 0u;
+    __syncthreads();
+    if (tid < TILE_ROWS) ws.bits[T * TILE_ROWS + tid] = sh.M[tid];
+    build_lines<0>(sh, tid);  // row runs (for the run table)
+    // nodes: runs (row connection) or single pixels
+    if (tid < TILE_ROWS) {
+        const uint64_t m = sh.M[tid];
+        const uint64_t ns = ROW ? (m & ~(m << 1)) : m;
+        sh.NS[tid] = ns;
+        const uint32_t c = popc64(ns);
+        uint32_t inc = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if (tid >= off) inc += o;
+        }
+        sh.nbase[tid] = inc - c;
+        if (tid == TILE_ROWS - 1) sh.nbase[TILE_ROWS] = inc;
+    }
+    __syncthreads();
+    const uint32_t N = sh.nbase[TILE_ROWS];
+    {
+        // node list, one 16-column window of a row per thread
+        const int l = tid >> 2, lo = (tid & 3) * 16;
+        uint32_t id = sh.nbase[l] + popc64(sh.NS[l] & ~(~0ull << lo));
+        for (uint32_t r = (uint32_t)(sh.NS[l] >> lo) & 0xffffu; r; r &= r - 1u, ++id)
+            sh.NL[id] = (uint16_t)((__builtin_ctz(r) + lo) | (l << 6));
+    }
+    __syncthreads();
+    uint32_t it = 0, at = 0;
+    // provisional labels; coarse column links
+    for (uint32_t id = tid; id < N; id += NT) {
+        const uint32_t rec = sh.NL[id];
+        const int s0 = rec & 63, l = rec >> 6;
+        const int e = ROW ? s0 + ctz64_or64(~(sh.M[l] >> s0)) - 1 : s0;
+        uint32_t v = pk((uint32_t)(l * TW + s0), id);
+        if (COL && l > 0) {
+            const uint64_t contact = sh.M[l - 1] & span_mask(s0, e);
+            if (contact) {
+                const uint64_t below = sh.NS[l - 1] & upto(ctz64(contact));
+                v = pk((uint32_t)((l - 1) * TW + msb64(below)), sh.nbase[l - 1] + popc64(below) - 1u);
+            }
+        }
+        sh.P[id] = v;
+    }
+    __syncthreads();
+    // label-equivalence unification
+    for (uint32_t id = tid; id < N; id += NT) lds_st(sh.P + id, pfind_count(sh.P, id, it));
+    // refinement edges: adjacencies the coarse structure does not hold
+    {
+        const int l = tid >> 2, lo = (tid & 3) * 16;
+        const uint64_t m = sh.M[l], ns = sh.NS[l];
+        uint64_t vert = 0, horz = 0;
+        if (l > 0) {
+            const uint64_t o = m & sh.M[l - 1];
+            // a column continues the previous column's edge when both nodes do
+            const uint64_t same = (o << 1) & o & ~ns & ~sh.NS[l - 1];
+            vert = o & ~same;
+            if (COL) {
+                // each node's first edge (leftmost contact above) is its coarse link
+                const uint64_t q = m & ~vert;
+                const uint64_t first = (ns & vert) | ((q + (ns & q)) & vert);
+                vert &= ~first;
+            }
+        }
+        if (!ROW) horz = m & (m << 1);  // pixel x joins pixel x - 1
+        const uint32_t wv = (uint32_t)(vert >> lo) & 0xffffu, wh = (uint32_t)(horz >> lo) & 0xffffu;
+        const uint32_t n = (uint32_t)__builtin_popcount(wv) + (uint32_t)__builtin_popcount(wh);
+        if (n) {
+            uint32_t off = atomicAdd(&sh.nedges, n);
+            for (uint32_t r = wv; r; r &= r - 1u, ++off) {
+                const int x = __builtin_ctz(r) + lo;
+                sh.EL[off] = abl_node(sh, l, x) | (abl_node(sh, l - 1, x) << 16);
+            }
+            for (uint32_t r = wh; r; r &= r - 1u, ++off) {
+                const int x = __builtin_ctz(r) + lo;
+                sh.EL[off] = abl_node(sh, l, x) | (abl_node(sh, l, x - 1) << 16);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t E = sh.nedges;
+    for (uint32_t k = tid; k < E; k += NT) {
+        const uint32_t ed = sh.EL[k];
+        punion_count(sh.P, ed & 0xffffu, ed >> 16, it, at);
+    }
+    __syncthreads();
+    for (uint32_t id = tid; id < N; id += NT) lds_st(sh.P + id, pfind_count(sh.P, id, it));
+    __syncthreads();
+
+    // border slots, representatives, forest nodes (as in k_local)
+    const int s = tid;
+    int sx, sy;
+    slot_xy(s, sx, sy);
+    const bool fg = (sh.M[sy] >> sx) & 1ull;
+    uint32_t root = 0, rkey = 0;
+    if (fg) {
+        const uint32_t v = lds_ld(sh.P + abl_node(sh, sy, sx));
+        root = pk_id(v);
+        rkey = pk_key(v);
+    }
+    __syncthreads();
+    if (fg)
+        __hip_atomic_fetch_max(sh.P + root, REP_TAG | (uint32_t)(NSLOTS - 1 - s),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    const int64_t sbase = T * NSLOTS;
+    {
+        int32_t node = -1;
+        if (fg) {
+            const int rep = NSLOTS - 1 - (int)pk_id(lds_ld(sh.P + root));
+            node = (int32_t)(sbase + rep);
+            if (rep == s) {
+                const uint32_t gkey = (uint32_t)((int64_t)(gy0 + (int)(rkey / TW)) * a.W +
+                                                 gx0 + (int)(rkey % TW));
+                ws.forest[node] = ((uint64_t)gkey << 32) | (uint32_t)node;
+            }
+        }
+        ws.slots[sbase + s] = node;
+    }
+    // run table over row runs: the entry of the node holding each run's first pixel
+    uint16_t* rtab = ws.runtab + T * RUNTAB_PER_TILE;
+    const uint32_t R = sh.base[TILE_ROWS];
+    for (uint32_t rid = tid; rid < R; rid += NT) {
+        // row of run rid: last row whose first run id is <= rid
+        int lo = 0, hi = TILE_ROWS - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sh.base[mid] <= rid) lo = mid;
+            else hi = mid - 1;
+        }
+        uint64_t ls = sh.LS[lo];
+        for (uint32_t k = rid - sh.base[lo]; k; --k) ls &= ls - 1ull;
+        const uint32_t id = abl_node(sh, lo, ctz64(ls));
+        const uint32_t v = lds_ld(sh.P + id);
+        uint16_t ent;
+        if (v & REP_TAG) {
+            ent = (uint16_t)(RT_BORDER | (NSLOTS - 1 - pk_id(v)));
+        } else {
+            const uint32_t w = pk_id(v) == id ? v : lds_ld(sh.P + pk_id(v));
+            ent = (w & REP_TAG) ? (uint16_t)(RT_BORDER | (NSLOTS - 1 - pk_id(w)))
+                                : (uint16_t)pk_key(v);
+        }
+        rtab[rid] = ent;
+    }
+    if (counters) {
+        atomicAdd(&sh.cit, it);
+        atomicAdd(&sh.cat, at);
+        __syncthreads();
+        if (tid == 0) {
+            counters[2 * T] = sh.cit;
+            counters[2 * T + 1] = sh.cat;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // copy kernel (bandwidth / counter calibration)
 // ---------------------------------------------------------------------------
 
@@ -1571,6 +1809,25 @@ hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipSt
 {
     if (conn == 8) return launch_all<1>(b, ws, st, timer, local_only, stats);
     return launch_all<0>(b, ws, st, timer, local_only, stats);
+}
+
+hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t st, int variant,
+                           uint32_t* counters)
+{
+    if (b.ntiles <= 0) return hipSuccess;
+    const unsigned g = (unsigned)b.ntiles;
+    switch (variant) {
+        case 0: k_local_ablate<ABL_ROW | ABL_COL><<<g, NT, 0, st>>>(b, ws, counters); break;
+        case 1: k_local_ablate<ABL_ROW><<<g, NT, 0, st>>>(b, ws, counters); break;
+        case 2: k_local_ablate<ABL_COL><<<g, NT, 0, st>>>(b, ws, counters); break;
+        default: k_local_ablate<0><<<g, NT, 0, st>>>(b, ws, counters); break;
+    }
+    if (b.ngroups > 0) k_block<0><<<(unsigned)b.ngroups, NTB, 0, st>>>(b, ws);
+    if (b.nseamwg > 0) k_seam<0><<<(unsigned)b.nseamwg, SEAM_WG, 0, st>>>(b, ws);
+    const unsigned fgrid =
+        (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<0, false, false>, NT));
+    k_final<0, false, false><<<fgrid, NT, 0, st>>>(b, ws, StatsWs{});
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_count(int64_t* count, hipStream_t st)

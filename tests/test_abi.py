@@ -93,6 +93,22 @@ def test_stats_validation(lib, args, status):
     assert b"ccl_label_stats" in lib.ccl_last_error()
 
 
+@pytest.mark.parametrize("args,status", [
+    ((FAKE_IMG, 4, 4, 4, 4, FAKE_OUT, None), -1),       # variant 4 does not exist
+    ((FAKE_IMG, 4, 4, 4, -1, FAKE_OUT, None), -1),      # negative variant
+    ((FAKE_IMG, -1, 4, 4, 0, FAKE_OUT, None), -1),      # negative height
+    ((FAKE_IMG, 4, 4, 4, 0, None, None), -1),           # null labels
+])
+def test_ablation_validation(lib, args, status):
+    f = lib.ccl_label_ablation
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.ccl_last_error.restype = ctypes.c_char_p
+    assert f(*args, None) == status
+    assert b"ccl_label_ablation" in lib.ccl_last_error()
+
+
 def test_batch_validation(lib):
     import paper_1712_09789_amd.ccl as c  # the binding loads on CPU too
     descs = (c.ImageDesc * 3)()
