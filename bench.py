@@ -309,6 +309,54 @@ def bench_stats(ccl, torch, dev, cases, devs, label_us, steps, check=True):
     return out
 
 
+def bench_ablation(ccl, torch, dev, check=True):
+    """The paper's study of its coarse step (4-connectivity): per-tile find
+    iterations and atomic merge attempts of C2FL / RC2FL / CC2FL / NC2FL
+    (means over tiles, and the largest tile) for Bernoulli p = 0.5 images of
+    32^2 .. 4096^2 and for densities 0.1 .. 0.9 at 2048^2, plus the time of
+    each variant's full labelling at 4096^2, p = 0.5."""
+    from paper_1712_09789_amd import workloads as wl
+    out = {"by_size_p0.5": {}, "by_density_2048": {}, "time_4096_us": {}, "exact": None}
+    exact = True
+
+    def counts(img, v):
+        d = torch.from_numpy(img).to(dev)
+        lab, cnt = ccl.label_ablation(d, v, counters=True)
+        c = cnt.cpu().numpy().astype(np.int64)
+        return lab, [round(float(c[:, 0].mean()), 1), round(float(c[:, 1].mean()), 1),
+                     int(c[:, 0].max()), int(c[:, 1].max())]
+
+    for v in ccl.ABLATIONS:
+        out["by_size_p0.5"][v] = {}
+        for n in (32, 64, 128, 256, 512, 1024, 2048, 4096):
+            img = wl.bernoulli(n, n, 0.5, seed=n)
+            lab, c = counts(img, v)
+            out["by_size_p0.5"][v][n] = c
+            if check and n == 512:
+                import oracle
+                exact &= bool(np.array_equal(lab.cpu().numpy(), oracle.oracle_label(img, 4)))
+        out["by_density_2048"][v] = {}
+        for p10 in range(1, 10):
+            img = wl.bernoulli(2048, 2048, p10 / 10, seed=p10)
+            out["by_density_2048"][v][p10 / 10] = counts(img, v)[1]
+    img = torch.from_numpy(wl.bernoulli(4096, 4096, 0.5, seed=0)).to(dev)
+    lab = torch.empty((4096, 4096), dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+    for v in ccl.ABLATIONS:
+        for _ in range(3):
+            ccl.label_ablation(img, v, out=lab)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(20):
+            ccl.label_ablation(img, v, out=lab)
+        e1.record(st)
+        torch.cuda.synchronize()
+        out["time_4096_us"][v] = round(1e3 * e0.elapsed_time(e1) / 20, 1)
+    out["exact"] = exact if check else None
+    out["columns"] = "[mean iterations per tile, mean atomics per tile, max iterations, max atomics]"
+    return out
+
+
 def bench_batch(ccl, torch, dev, check=True, n=256, reps=5):
     """256 uint8 images, sides log-uniform in [64, 2048], half Bernoulli and
     half blobs at random density, 8-connectivity: one ccl_label_batch call
@@ -612,6 +660,8 @@ def main():
         result["stats_4096"] = bench_stats(ccl, torch, dev, cases, devs, 1e3 * ms_step,
                                            min(args.steps, 140), check=cpu is not None)
         log(f"[bench] stats: {result['stats_4096']}")
+        result["ablation"] = bench_ablation(ccl, torch, dev, check=cpu is not None)
+        log(f"[bench] ablation: {result['ablation']['time_4096_us']} exact {result['ablation']['exact']}")
         result["batch_256"] = bench_batch(ccl, torch, dev, check=cpu is not None)
         log(f"[bench] batch: {result['batch_256']}")
         result["serving"] = bench_serving(torch, dev)
