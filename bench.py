@@ -205,6 +205,32 @@ def step_distribution(ccl, torch, devs, steps):
             "p99": round(float(np.percentile(us, 99)), 2), "reps": steps}
 
 
+def multi_stream_rate(ccl, torch, devs, steps, nstreams=4):
+    """Gpixel/s when the rotation's independent images are issued round-robin
+    on `nstreams` streams (each with its own workspace), so that the merge
+    and final kernels of one image overlap the local step of the next.  A
+    throughput figure beside the one-stream headline, not a replacement."""
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    cur = torch.cuda.current_stream()
+    for i in range(2 * nstreams):
+        img, out, conn = devs[i % len(devs)]
+        ccl.label(img, conn, out=out, stream=streams[i % nstreams])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(cur)
+    for st in streams:
+        st.wait_stream(cur)
+    for i in range(steps):
+        img, out, conn = devs[i % len(devs)]
+        ccl.label(img, conn, out=out, stream=streams[i % nstreams])
+    for st in streams:
+        cur.wait_stream(st)
+    e1.record(cur)
+    torch.cuda.synchronize()
+    px = devs[0][0].shape[0] * devs[0][0].shape[1]
+    return steps * px / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+
 def copy_bandwidth(ccl, torch, dev, mib=256, reps=10):
     """Read + write GB/s of the library's copy kernel over `mib` MiB: the
     achievable HBM rate on this machine, next to the 8 TB/s peak."""
@@ -591,6 +617,7 @@ def main():
     dom = max(("local", "final"), key=lambda k: kavg.get(k, 0.0))
     _, kdom = time_rotation(ccl, torch, devs, args.steps, args.warmup, timing=[dom])
     dist = step_distribution(ccl, torch, devs, max(args.steps, 20))
+    streams4 = multi_stream_rate(ccl, torch, devs, args.steps)
     copy_gbs = copy_bandwidth(ccl, torch, dev)
     px = size * size
     value = args.steps * px / secs / 1e9
@@ -625,6 +652,7 @@ def main():
                                "connectivity 4 and 8; 14 resident buffer sets in rotation",
                    "tile": list(ccl.tile_shape())},
         "step_us": dist,
+        "streams_4_Gpx/s": round(streams4, 1),
         "path_hbm_frac": round(PATH_BYTES_PER_PX * value / HBM_PEAK_GBS, 4),
         "copy_GBs": round(copy_gbs, 1),
         "path_copy_frac": round(PATH_BYTES_PER_PX * value / copy_gbs, 4),

@@ -358,6 +358,48 @@ __device__ __forceinline__ V ld_uniform(const V* p)
 #endif
 }
 
+// Caller buffers (image, labels, statistics) are reached through pointers
+// read from memory, which the compiler cannot place in an address space, so
+// it would use flat instructions; flat accesses also count against the LDS
+// wait counter, and every LDS wait would then wait for them too (the
+// next-tile prefetch and the label stores included).  These accessors name
+// the global address space explicitly.
+template <typename V>
+__device__ __forceinline__ V ld_global(const V* p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(1))) V*)p;
+#else
+    return *p;  // host pass: never executed
+#endif
+}
+template <typename V>
+__device__ __forceinline__ void st_global(V* p, const V& v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    *(__attribute__((address_space(1))) V*)p = v;
+#else
+    *p = v;  // host pass: never executed
+#endif
+}
+// 16-byte accesses go through plain vector types: the copy of HIP's uint4 /
+// int4 classes would turn the global lvalue back into a generic one.
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_global16(const void* p)
+{
+    const v4u32 v = ld_global(reinterpret_cast<const v4u32*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_global16(void* p, int32_t a, int32_t b, int32_t c, int32_t d)
+{
+    v4u32 v;
+    v.x = (uint32_t)a;
+    v.y = (uint32_t)b;
+    v.z = (uint32_t)c;
+    v.w = (uint32_t)d;
+    st_global(reinterpret_cast<v4u32*>(p), v);
+}
+
 __device__ __forceinline__ ImageArgs batch_image(const BatchArgs& b, int i)
 {
     return b.n == 1 ? b.one : ld_uniform(b.imgs + i);
@@ -405,11 +447,11 @@ __device__ __forceinline__ uint4 fetch_chunk(const ImageArgs& a, int t, int c)
     if (gy < a.H && gx < a.W) {
         const uint8_t* src = a.img + (int64_t)gy * a.pitch + gx;
         if (a.vec_in && gx + 16 <= a.W) {
-            v = *reinterpret_cast<const uint4*>(src);
+            v = ld_global16(src);
         } else {
             const int n = a.W - gx < 16 ? a.W - gx : 16;
             uint32_t w[4] = {0u, 0u, 0u, 0u};
-            for (int i = 0; i < n; ++i) w[i >> 2] |= (uint32_t)src[i] << (8 * (i & 3));
+            for (int i = 0; i < n; ++i) w[i >> 2] |= (uint32_t)ld_global(src + i) << (8 * (i & 3));
             v = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
@@ -1061,10 +1103,10 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
         }
         int32_t* dst = a.labels + (int64_t)gy * a.W + gx0 + x0;
         if (a.vec_out && x0 + 4 <= xmax) {
-            *reinterpret_cast<int4*>(dst) = make_int4(o[0], o[1], o[2], o[3]);
+            st_global16(dst, o[0], o[1], o[2], o[3]);
         } else {
             const int n = xmax - x0 < 4 ? xmax - x0 : 4;
-            for (int k = 0; k < n; ++k) dst[k] = o[k];
+            for (int k = 0; k < n; ++k) st_global(dst + k, o[k]);
         }
     }
 }
@@ -1155,14 +1197,15 @@ __global__ __launch_bounds__(SCAN_T) void k_scan2(StatsWs st)
         if (i < st.nblk) st.boff[i] = (uint32_t)(carry + inc - v);
         carry += total;
     }
-    if (threadIdx.x == 0) *st.count = (int64_t)carry;
+    if (threadIdx.x == 0) st_global(st.count, (int64_t)carry);
 }
 
 // Neutral values for the accumulating fields of every numbered component
 // that fits the caller's array.
 __global__ __launch_bounds__(256) void k_stats_init(StatsWs st)
 {
-    const int64_t n = *st.count < st.capacity ? *st.count : st.capacity;
+    const int64_t cnt = ld_global(st.count);
+    const int64_t n = cnt < st.capacity ? cnt : st.capacity;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         CompStats c;
@@ -1171,7 +1214,7 @@ __global__ __launch_bounds__(256) void k_stats_init(StatsWs st)
         c.x_min = c.y_min = INT32_MAX;
         c.x_max = c.y_max = -1;
         c.sum_x = c.sum_y = 0;
-        st.comps[i] = c;
+        st_global(st.comps + i, c);
     }
 }
 
@@ -1291,7 +1334,7 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
             key = top ? (uint32_t)(2 * l * TW + ctz64(top)) : (uint32_t)((2 * l + 1) * TW + s0);
         }
         const int64_t kpos = (int64_t)(gy0 + (int)(key / TW)) * a.W + gx0 + (int)(key % TW);
-        const int32_t L = a.labels[kpos];
+        const int32_t L = ld_global(a.labels + kpos);
         if (L <= 0 || (int64_t)L > kpos + 1) continue;  // not a label of this pixel
         const bool is_root = kpos == (int64_t)L - 1;
         const uint32_t en = sh.ent[id];
@@ -1325,8 +1368,8 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         const int64_t num = component_number(a, st, L);
         if (num >= st.capacity) continue;
         CompStats* c = st.comps + num;
-        c->label = L;
-        c->y_min = (int32_t)(kpos / a.W);
+        st_global(&c->label, L);
+        st_global(&c->y_min, (int32_t)(kpos / a.W));
     }
     __syncthreads();
     // interior components: the whole entry from the run holding the smallest pixel
@@ -1356,7 +1399,7 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         c.y_max = gy0 + sh.iymax[id];
         c.sum_x = (int64_t)(sh.isx[id] + (uint64_t)area * gx0);
         c.sum_y = (int64_t)(sh.isy[id] + (uint64_t)area * gy0);
-        st.comps[num] = c;
+        st_global(st.comps + num, c);
     }
     // one partial record per border component of the tile
     const int area = tid < NSLOTS ? sh.area[tid] : 0;
@@ -1469,7 +1512,7 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
     }
 }
 
-__global__ void k_zero_count(int64_t* count) { *count = 0; }
+__global__ void k_zero_count(int64_t* count) { st_global(count, (int64_t)0); }
 
 // ---------------------------------------------------------------------------
 // ablations of the local step (4-connectivity, the paper's setting)
