@@ -53,13 +53,14 @@ struct Workspace {
     int32_t* slots;    // [ntiles][NSLOTS] forest node of each border pixel, -1 = bg
     uint64_t* forest;  // [ntiles][NSLOTS] (key of parent << 32) | parent node
     uint16_t* runtab;  // [ntiles][RUNTAB_PER_TILE] local root of each run
+    uint32_t* nruns;   // [ntiles] runs of each tile (valid run-table entries)
 };
 
 inline int64_t workspace_bytes(int64_t ntiles)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     return up(ntiles * TILE_ROWS * 8) + up(ntiles * NSLOTS * 4) + up(ntiles * NSLOTS * 8) +
-           up(ntiles * RUNTAB_PER_TILE * 2);
+           up(ntiles * RUNTAB_PER_TILE * 2) + up(ntiles * 4);
 }
 
 inline Workspace carve_workspace(void* base, int64_t ntiles)
@@ -74,6 +75,8 @@ inline Workspace carve_workspace(void* base, int64_t ntiles)
     ws.forest = reinterpret_cast<uint64_t*>(p);
     p += up(ntiles * NSLOTS * 8);
     ws.runtab = reinterpret_cast<uint16_t*>(p);
+    p += up(ntiles * RUNTAB_PER_TILE * 2);
+    ws.nruns = reinterpret_cast<uint32_t*>(p);
     return ws;
 }
 

@@ -11,17 +11,25 @@
 // strip run is a node.  "Line" below means a row (4-connectivity) or a strip
 // (8-connectivity); runs get dense ids in line-major, left-to-right order.
 //
-// Three kernels per image (the paper's Section 3):
+// Four kernels per image (the paper's Section 3):
 //   k_local  (Section 3.1)  load the tile, label it in LDS, and publish what
 //            the merge and the relabel need: the foreground bitmask, a run
 //            table (local root of each run), one forest node id per border
 //            pixel, and one forest node per component that touches the tile
 //            border.
-//   k_seam   (Section 3.2)  for every foreground pair straddling a tile seam,
-//            unite the two components' forest nodes in HBM (atomicMin).
+//   k_block  (Section 3.2, inside groups of 4 x 4 tiles)  unite the border
+//            nodes across the seams inside the group in LDS and write the
+//            group roots to the forest.
+//   k_seam   (Section 3.2, between groups)  for every foreground pair
+//            straddling a group seam, unite the two group roots in HBM
+//            (atomicMin).
 //   k_final  (Section 3.3)  look up the global root of each border component
 //            and write every label exactly once, from the bitmask and the run
 //            table (no union-find work is repeated).
+// Batches of images share one launch of each (k_index maps tiles, groups and
+// seam workgroups to their image).  Optional extras: per-component statistics
+// (k_scan1/2, k_stats_init, k_stats, k_stats_merge) and the paper's ablation
+// variants of the local step (k_local_ablate).
 //
 // Labels are canonical: 1 + the smallest raster position of the component.
 // Every node carries a key, the tile position of its smallest pixel; parents
@@ -337,10 +345,6 @@ constexpr uint16_t RT_BORDER = 0x8000;
 constexpr uint32_t REP_TAG = 0x80000000u;
 
 // ---------------------------------------------------------------------------
-// k_local
-// ---------------------------------------------------------------------------
-
-// ---------------------------------------------------------------------------
 // images of a batch
 // ---------------------------------------------------------------------------
 
@@ -435,6 +439,10 @@ __global__ __launch_bounds__(256) void k_index(BatchArgs b)
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_local
+// ---------------------------------------------------------------------------
+
 // Initialisation (Section 3.1.1): sixteen bytes of a tile, four threads per
 // row.  Bytes past the image edge read as background.  The raw bytes are
 // returned so that the load of the next tile can be in flight while the
@@ -486,6 +494,7 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
     // tid + 256, ...) so that every lane has work; only two cheap passes walk
     // the bits of a column window: the run list and the refinement edge list.
     const uint32_t R = sh.base[G::NL];
+    if (tid == 0) ws.nruns[T] = R;
     const int wl = tid / G::TPL;              // this thread's line
     const int wlo = (tid % G::TPL) * G::WIN;  // and first column of its window
     constexpr uint32_t WMASK = (1u << G::WIN) - 1u;
@@ -995,22 +1004,22 @@ struct FinalShared : Lines<D> {
 };
 static_assert(RUNTAB_PER_TILE == 8 * NT, "one 16-byte run-table load per thread");
 
-// Loads of one tile for k_final that depend on no other: the border slot of
-// this thread, the row masks and the whole run table (eight entries per
-// thread; entries past the run count are unused).
 struct FinalFetch {
     int32_t node;
+    uint32_t nruns;
     uint64_t m;
-    uint4 ent;
 };
 
+// Loads of one tile for k_final that depend on no other: the border slot of
+// this thread, the row masks and the run count (which sizes the run-table
+// load issued when the tile's turn comes).
 __device__ __forceinline__ FinalFetch final_fetch(const Workspace& ws, int64_t T, int tid)
 {
     static_assert(NSLOTS == NT, "one border slot per thread");
     FinalFetch f;
     f.node = ws.slots[T * NSLOTS + tid];
+    f.nruns = ws.nruns[T];
     f.m = tid < TILE_ROWS ? ws.bits[T * TILE_ROWS + tid] : 0ull;
-    f.ent = reinterpret_cast<const uint4*>(ws.runtab + T * RUNTAB_PER_TILE)[tid];
     return f;
 }
 
@@ -1028,8 +1037,12 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
-    // The first forest hop is issued before the line set-up, so the chase
-    // to the global root overlaps it.
+    // The run table (only the chunks holding the tile's runs, eight entries
+    // per thread) and the first forest hop are issued before the line set-up,
+    // so their latency overlaps it.
+    uint4 ent = make_uint4(0u, 0u, 0u, 0u);
+    if (8u * tid < f.nruns)
+        ent = reinterpret_cast<const uint4*>(ws.runtab + T * RUNTAB_PER_TILE)[tid];
     uint64_t v = f.node >= 0 ? ws.forest[f.node] : 0;
     if (tid < TILE_ROWS) {
         sh.M[tid] = f.m;
@@ -1038,7 +1051,7 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
     __syncthreads();
     build_lines<D>(sh, tid);
     const uint32_t R = sh.base[Geo<D>::NL];
-    reinterpret_cast<uint4*>(sh.ent)[tid] = f.ent;
+    reinterpret_cast<uint4*>(sh.ent)[tid] = ent;
     // Global root of the component at this border slot.  The slot names a
     // forest node of that component (its tile representative, or the group
     // root after the block merge); before any merge the node is the root.
@@ -1568,6 +1581,7 @@ __global__ __launch_bounds__(NT) void k_local_ablate(BatchArgs b, Workspace ws, 
     __syncthreads();
     if (tid < TILE_ROWS) ws.bits[T * TILE_ROWS + tid] = sh.M[tid];
     build_lines<0>(sh, tid);  // row runs (for the run table)
+    if (tid == 0) ws.nruns[T] = sh.base[TILE_ROWS];
     // nodes: runs (row connection) or single pixels
     if (tid < TILE_ROWS) {
         const uint64_t m = sh.M[tid];
