@@ -617,7 +617,9 @@ def main():
     dom = max(("local", "final"), key=lambda k: kavg.get(k, 0.0))
     _, kdom = time_rotation(ccl, torch, devs, args.steps, args.warmup, timing=[dom])
     dist = step_distribution(ccl, torch, devs, max(args.steps, 20))
-    streams4 = multi_stream_rate(ccl, torch, devs, args.steps)
+    # (after the timed regions, and left out of profiled runs: concurrent
+    # kernels would blur per-kernel durations)
+    streams4 = None if args.no_extra else multi_stream_rate(ccl, torch, devs, args.steps)
     copy_gbs = copy_bandwidth(ccl, torch, dev)
     px = size * size
     value = args.steps * px / secs / 1e9
@@ -652,7 +654,7 @@ def main():
                                "connectivity 4 and 8; 14 resident buffer sets in rotation",
                    "tile": list(ccl.tile_shape())},
         "step_us": dist,
-        "streams_4_Gpx/s": round(streams4, 1),
+        "streams_4_Gpx/s": round(streams4, 1) if streams4 else None,
         "path_hbm_frac": round(PATH_BYTES_PER_PX * value / HBM_PEAK_GBS, 4),
         "copy_GBs": round(copy_gbs, 1),
         "path_copy_frac": round(PATH_BYTES_PER_PX * value / copy_gbs, 4),
