@@ -51,6 +51,11 @@ def _load():
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_int32, ctypes.c_void_p,
         ]
+        lib.oracle_label3d.restype = ctypes.c_int
+        lib.oracle_label3d.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+        ]
         _lib = lib
     return _lib
 
@@ -74,6 +79,29 @@ def oracle_label(img: np.ndarray, connectivity: int = 8) -> np.ndarray:
                               out.ctypes.data)
     if rc != 0:
         raise ValueError(f"oracle_label failed with status {rc}")
+    return out
+
+
+def oracle_label3d(vol: np.ndarray, connectivity: int = 26) -> np.ndarray:
+    """Canonical labels of a 3-D uint8 volume indexed [z, y, x] (nonzero =
+    foreground), 6- or 26-connectivity: 0 for background, else 1 + the
+    smallest position x + y * W + z * W * H in the component.  Rows must be
+    contiguous; the row and slice pitches come from the strides."""
+    if vol.ndim != 3 or vol.dtype != np.uint8:
+        raise ValueError("oracle_label3d expects a 3-D uint8 array")
+    D, H, W = vol.shape
+    out = np.zeros((D, H, W), dtype=np.int32)
+    if D == 0 or H == 0 or W == 0:
+        return out
+    if (vol.strides[2] != 1 or (H > 1 and vol.strides[1] < W)
+            or (D > 1 and vol.strides[0] < (H - 1) * vol.strides[1] + W)):
+        vol = np.ascontiguousarray(vol)
+    pitch = vol.strides[1] if H > 1 else W
+    slice_pitch = vol.strides[0] if D > 1 else H * pitch  # a length-1 axis may carry any stride
+    rc = _load().oracle_label3d(vol.ctypes.data, D, H, W, pitch, slice_pitch,
+                                int(connectivity), out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_label3d failed with status {rc}")
     return out
 
 

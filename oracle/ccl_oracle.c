@@ -112,3 +112,81 @@ int oracle_label(const uint8_t* img, int64_t H, int64_t W, int64_t pitch,
     free(parent);
     return ORACLE_OK;
 }
+
+/*
+ * Volumes.  The paper's introduction names 2-D and 3-D images as the inputs
+ * of connected-components labelling; the definition carries over with the
+ * voxel position P(x, y, z) = x + y * W + z * W * H:
+ *
+ *   fg(x, y, z) = vol[z * slice_pitch + y * pitch + x] != 0
+ *   6-connectivity:  face neighbours        (|dx| + |dy| + |dz| = 1)
+ *   26-connectivity: the 3 x 3 x 3 block    (max(|dx|, |dy|, |dz|) = 1)
+ *   L = 0 for background, otherwise 1 + the smallest position in the
+ *       component.
+ *
+ * Same two passes as above: in raster order (z, then y, then x) each fg voxel
+ * is united with its already-visited fg neighbours (6: left, up, previous
+ * slice; 26: left, the three voxels of the row above, and the nine voxels of
+ * the previous slice), the larger root pointing at the smaller.
+ */
+int oracle_label3d(const uint8_t* vol, int64_t D, int64_t H, int64_t W, int64_t pitch,
+                   int64_t slice_pitch, int32_t connectivity, int32_t* out)
+{
+    if (D < 0 || H < 0 || W < 0) return ORACLE_ERR_ARG;
+    if (connectivity != 6 && connectivity != 26) return ORACLE_ERR_ARG;
+    if (D == 0 || H == 0 || W == 0) return ORACLE_OK;
+    if (vol == NULL || out == NULL || pitch < W || slice_pitch < (H - 1) * pitch + W)
+        return ORACLE_ERR_ARG;
+    if (D * H * W > (int64_t)INT32_MAX) return ORACLE_ERR_ARG;
+
+    const int64_t n = D * H * W, S = H * W;
+    int64_t* parent = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (parent == NULL) return ORACLE_ERR_MEM;
+#define FG(x, y, z) (vol[(z) * slice_pitch + (y) * pitch + (x)] != 0)
+
+    /* pass 1 */
+    for (int64_t z = 0; z < D; ++z) {
+        for (int64_t y = 0; y < H; ++y) {
+            for (int64_t x = 0; x < W; ++x) {
+                const int64_t p = z * S + y * W + x;
+                parent[p] = p;
+                if (!FG(x, y, z)) continue;
+                if (connectivity == 6) {
+                    if (x > 0 && FG(x - 1, y, z)) unite(parent, p, p - 1);
+                    if (y > 0 && FG(x, y - 1, z)) unite(parent, p, p - W);
+                    if (z > 0 && FG(x, y, z - 1)) unite(parent, p, p - S);
+                    continue;
+                }
+                if (x > 0 && FG(x - 1, y, z)) unite(parent, p, p - 1);
+                if (y > 0) {
+                    for (int64_t dx = -1; dx <= 1; ++dx) {
+                        const int64_t xx = x + dx;
+                        if (xx >= 0 && xx < W && FG(xx, y - 1, z)) unite(parent, p, p - W + dx);
+                    }
+                }
+                if (z > 0) {
+                    for (int64_t dy = -1; dy <= 1; ++dy) {
+                        const int64_t yy = y + dy;
+                        if (yy < 0 || yy >= H) continue;
+                        for (int64_t dx = -1; dx <= 1; ++dx) {
+                            const int64_t xx = x + dx;
+                            if (xx >= 0 && xx < W && FG(xx, yy, z - 1))
+                                unite(parent, p, p - S + dy * W + dx);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    /* pass 2 */
+    for (int64_t z = 0; z < D; ++z)
+        for (int64_t y = 0; y < H; ++y)
+            for (int64_t x = 0; x < W; ++x) {
+                const int64_t p = z * S + y * W + x;
+                out[p] = FG(x, y, z) ? (int32_t)(find_root(parent, p) + 1) : 0;
+            }
+#undef FG
+    free(parent);
+    return ORACLE_OK;
+}

@@ -62,3 +62,36 @@ def unstack_labels(labels: np.ndarray, k: int, h: int, w: int) -> np.ndarray:
     lab = labels.reshape(k, h + 1, w)[:, :h, :].astype(np.int64)
     base = (np.arange(k, dtype=np.int64) * (h + 1) * w)[:, None, None]
     return np.where(lab > 0, lab - base, 0).astype(np.int32)
+
+
+def bfs_label3d(vol: np.ndarray, connectivity: int) -> np.ndarray:
+    """Flood fill of a [z, y, x] volume, seeds in raster order (so the label
+    is 1 + the seed's position x + y*W + z*W*H)."""
+    D, H, W = vol.shape
+    fg = (np.asarray(vol) != 0)
+    out = np.zeros((D, H, W), dtype=np.int64)
+    if connectivity == 6:
+        nbrs = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                if abs(dz) + abs(dy) + abs(dx) == 1]
+    elif connectivity == 26:
+        nbrs = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                if (dz, dy, dx) != (0, 0, 0)]
+    else:
+        raise ValueError(connectivity)
+    for z0 in range(D):
+        for y0 in range(H):
+            for x0 in range(W):
+                if not fg[z0, y0, x0] or out[z0, y0, x0]:
+                    continue
+                lab = z0 * H * W + y0 * W + x0 + 1
+                out[z0, y0, x0] = lab
+                q = deque([(z0, y0, x0)])
+                while q:
+                    z, y, x = q.popleft()
+                    for dz, dy, dx in nbrs:
+                        zz, yy, xx = z + dz, y + dy, x + dx
+                        if (0 <= zz < D and 0 <= yy < H and 0 <= xx < W and fg[zz, yy, xx]
+                                and not out[zz, yy, xx]):
+                            out[zz, yy, xx] = lab
+                            q.append((zz, yy, xx))
+    return out.astype(np.int32)
