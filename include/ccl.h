@@ -140,6 +140,27 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
                     int64_t capacity, int64_t* count, void* stream);
 
 /*
+ * Label a volume (the paper's introduction names 2-D and 3-D images): voxel
+ * position P = x + y * W + z * W * H; labels[P] = 0 for background, else 1 +
+ * the smallest position in the voxel's component.  The slices are labelled
+ * with the 2-D method (one batch), then components are united across
+ * adjacent slices (the block merge with slices as blocks) and every label is
+ * rewritten to its root.
+ *   vol           device, uint8, D slices of H rows; row y of slice z starts
+ *                 at vol + z * slice_pitch_bytes + y * pitch_bytes;
+ *                 caller-owned, only read.
+ *   pitch_bytes   >= W; slice_pitch_bytes >= (H - 1) * pitch_bytes + W
+ *                 (ignored when D == 1).
+ *   connectivity  6 (face neighbours) or 26 (the 3 x 3 x 3 block).
+ *   labels        device, int32, dense D * H * W; caller-owned, fully
+ *                 overwritten.  Must not overlap vol.
+ * Errors as ccl_label (CCL_ERR_TOO_LARGE when D * H * W > 2^31 - 1); an empty
+ * volume is a no-op.
+ */
+int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pitch_bytes,
+                 int64_t slice_pitch_bytes, int32_t connectivity, int32_t* labels, void* stream);
+
+/*
  * The paper's ablation of its local step (Section 4, effectiveness of coarse
  * labelling), for study rather than speed: the local step is rerun with the
  * coarse labelling along rows and columns (CCL_C2FL, the method), along rows

@@ -55,6 +55,8 @@ def _load() -> ctypes.CDLL:
         f.argtypes = [vp, i32, i32, i64, i32, vp, vp]
     lib.ccl_label_stats.restype = ctypes.c_int
     lib.ccl_label_stats.argtypes = [vp, i32, i32, i64, i32, vp, vp, i64, vp, vp]
+    lib.ccl_label_3d.restype = ctypes.c_int
+    lib.ccl_label_3d.argtypes = [vp, i32, i32, i32, i64, i64, i32, vp, vp]
     lib.ccl_label_ablation.restype = ctypes.c_int
     lib.ccl_label_ablation.argtypes = [vp, i32, i32, i64, i32, vp, vp, vp]
     lib.ccl_label_batch.restype = ctypes.c_int
@@ -169,6 +171,30 @@ def components_to_numpy(comps: torch.Tensor, count: torch.Tensor) -> np.ndarray:
     n = min(int(count.item()), comps.numel() // COMPONENT_DTYPE.itemsize)
     raw = comps[:n * COMPONENT_DTYPE.itemsize].cpu().numpy()
     return raw.view(COMPONENT_DTYPE).copy()
+
+
+def label_3d(vol: torch.Tensor, connectivity: int = 26, out: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+    """Canonical labels of a uint8 device volume indexed [z, y, x]
+    (ccl_label_3d; 6- or 26-connectivity)."""
+    if vol.dim() != 3 or vol.dtype != torch.uint8:
+        raise ValueError("volume must be a 3-D torch.uint8 tensor")
+    if not vol.is_cuda:
+        raise ValueError("volume must be a device (cuda) tensor")
+    D, H, W = vol.shape
+    if D > 0 and H > 0 and W > 1 and vol.stride(2) != 1:
+        raise ValueError("volume rows must be contiguous (stride(2) == 1)")
+    pitch = max(vol.stride(1) if H > 1 else W, W)
+    slice_pitch = vol.stride(0) if D > 1 else H * pitch
+    if out is None:
+        out = torch.empty((D, H, W), dtype=torch.int32, device=vol.device)
+    elif out.shape != (D, H, W) or out.dtype != torch.int32 or not out.is_contiguous() \
+            or out.device != vol.device:
+        raise ValueError("out must be a contiguous int32 tensor of the volume's shape "
+                         "on the volume's device")
+    _check(_lib.ccl_label_3d(vol.data_ptr(), D, H, W, pitch, slice_pitch, int(connectivity),
+                             out.data_ptr(), _stream_handle(stream)))
+    return out
 
 
 def label_ablation(img: torch.Tensor, variant: str = "C2FL", out: torch.Tensor | None = None,

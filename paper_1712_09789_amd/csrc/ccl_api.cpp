@@ -169,10 +169,11 @@ static ImageArgs make_args(const uint8_t* img, int32_t H, int32_t W, int64_t pit
     a.W = W;
     a.ntx = (W + TW - 1) / TW;
     a.nty = (H + TILE_ROWS - 1) / TILE_ROWS;
-    a.conn = conn;
+    (void)conn;  // the launch carries the connectivity (one per batch class)
     a.vec_in = ((uintptr_t)img % 16 == 0) && (pitch % 16 == 0);
     a.vec_out = ((uintptr_t)labels % 16 == 0) && (W % 4 == 0);
     a.wmagic = W == 1 ? 0xffffffffu : (uint32_t)((1ull << 32) / (uint64_t)W);
+    a.lbase = 0;
     a.tbase = 0;
     return a;
 }
@@ -368,6 +369,54 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
     std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, connectivity, labels));
     StatsOut so{comps, capacity, count};
     return run_batch(one, connectivity, st, false, who, &so);
+}
+
+int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pitch_bytes,
+                 int64_t slice_pitch_bytes, int32_t connectivity, int32_t* labels, void* stream)
+{
+    g_err.clear();
+    const char* who = "ccl_label_3d";
+    if (D < 0 || H < 0 || W < 0)
+        return fail(CCL_ERR_INVALID_ARG, "%s: negative size %dx%dx%d", who, D, H, W);
+    if (connectivity != 6 && connectivity != 26)
+        return fail(CCL_ERR_INVALID_ARG, "%s: connectivity %d is not 6 or 26", who, connectivity);
+    if (D == 0 || H == 0 || W == 0) return CCL_OK;
+    if ((int64_t)D * H * W > (int64_t)INT32_MAX)
+        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%dx%d voxels exceed int32 labels", who, D, H, W);
+    if (!vol || !labels) return fail(CCL_ERR_INVALID_ARG, "%s: null pointer", who);
+    if (pitch_bytes < W)
+        return fail(CCL_ERR_INVALID_ARG, "%s: pitch %lld < width %d", who, (long long)pitch_bytes, W);
+    if (D > 1 && slice_pitch_bytes < (int64_t)(H - 1) * pitch_bytes + W)
+        return fail(CCL_ERR_INVALID_ARG, "%s: slice pitch %lld is smaller than a slice", who,
+                    (long long)slice_pitch_bytes);
+    const uintptr_t v0 = (uintptr_t)vol,
+                    v1 = v0 + (uintptr_t)((int64_t)(D - 1) * slice_pitch_bytes +
+                                          (int64_t)(H - 1) * pitch_bytes + W);
+    const uintptr_t l0 = (uintptr_t)labels, l1 = l0 + (uintptr_t)((int64_t)D * H * W * 4);
+    if (v0 < l1 && l0 < v1) return fail(CCL_ERR_INVALID_ARG, "%s: vol and labels overlap", who);
+    const int conn2 = connectivity == 6 ? 4 : 8;  // the in-slice part of the neighbourhood
+    std::vector<ImageArgs> slices;
+    slices.reserve(D);
+    for (int32_t z = 0; z < D; ++z) {
+        ImageArgs a = make_args(vol + (int64_t)z * slice_pitch_bytes, H, W, pitch_bytes, conn2,
+                                labels + (int64_t)z * H * W);
+        a.lbase = (int32_t)((int64_t)z * H * W);
+        slices.push_back(a);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = run_batch(slices, conn2, st, false, who);
+    if (rc != CCL_OK) return rc;
+    VolArgs v;
+    v.vol = vol;
+    v.pitch = pitch_bytes;
+    v.slice_pitch = slice_pitch_bytes;
+    v.labels = labels;
+    v.D = D;
+    v.H = H;
+    v.W = W;
+    hipError_t e = launch_volume(v, connectivity, st);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return CCL_OK;
 }
 
 int ccl_label_ablation(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,

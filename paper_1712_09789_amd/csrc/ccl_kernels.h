@@ -23,11 +23,22 @@ struct ImageArgs {
     int32_t* labels;  // dense H x W
     int32_t H, W;
     int32_t ntx, nty;  // tile grid
-    int32_t conn;      // 4 or 8
+    uint32_t wmagic;   // floor(2^32 / W) (0xffffffff for W = 1), for division by W
+    int32_t lbase;     // added to every label written (a slice's first voxel position)
     int32_t vec_in;    // img and pitch are 16-byte aligned
     int32_t vec_out;   // labels rows are 16-byte aligned (W % 4 == 0)
-    uint32_t wmagic;   // floor(2^32 / W) (0xffffffff for W = 1), for division by W
     int64_t tbase;     // global index of the image's first tile in the workspace
+};
+// 64 bytes: the kernels read an image's entry with one scalar load.
+static_assert(sizeof(ImageArgs) == 64, "ImageArgs is one 64-byte scalar load");
+
+// A volume whose slices were labelled as a batch of images (labels lifted to
+// voxel positions by lbase).
+struct VolArgs {
+    const uint8_t* vol;
+    int64_t pitch, slice_pitch;  // bytes between rows / slices
+    int32_t* labels;             // dense D x H x W
+    int32_t D, H, W;
 };
 
 // Images labelled by one set of launches (all of one connectivity).  With n
@@ -184,6 +195,9 @@ hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipSt
 // the usual merge and final kernels; `counters` (2 per tile) may be null.
 hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t st, int variant,
                            uint32_t* counters);
+// Unite components across adjacent slices of a volume (6- or 26-connectivity)
+// and write canonical labels; the slices' labels must already be in place.
+hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st);
 // Writes *count = 0 (an empty image has no components).
 hipError_t launch_zero_count(int64_t* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,

@@ -1063,7 +1063,7 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
                 v = ws.forest[n];
             }
         }
-        sh.fin[tid] = (int32_t)((uint32_t)(v >> 32) + 1u);
+        sh.fin[tid] = (int32_t)((uint32_t)(v >> 32) + 1u) + a.lbase;
     }
     __syncthreads();
     for (uint32_t id = tid; id < R; id += NT) {
@@ -1072,7 +1072,8 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
         // interior component's local root
         sh.lab[id] = (e & RT_BORDER)
                          ? sh.fin[e & 0x7fff]
-                         : (int32_t)((int64_t)(gy0 + (int)(e / TW)) * a.W + gx0 + (int)(e % TW) + 1);
+                         : (int32_t)((int64_t)(gy0 + (int)(e / TW)) * a.W + gx0 + (int)(e % TW) + 1 +
+                                     a.lbase);
     }
     __syncthreads();
 
@@ -1735,6 +1736,118 @@ __global__ __launch_bounds__(NT) void k_local_ablate(BatchArgs b, Workspace ws, 
 }
 
 // ---------------------------------------------------------------------------
+// volumes
+// ---------------------------------------------------------------------------
+
+// The slices of a volume are labelled as a batch of images (4-connectivity
+// for 6, 8 for 26: the in-slice part of the neighbourhood), each label
+// lifted to 1 + a voxel position.  The label map is then itself the forest
+// of the merge across slices (the paper's block merge, with slices as the
+// blocks): every voxel's entry is 1 + an ancestor's position, the smallest
+// voxel of each slice component starts as a root, and a merge points the
+// larger root at the smaller with an atomic min, so entries only decrease.
+
+__device__ __forceinline__ uint32_t vl_ld(const int32_t* p)
+{
+    return (uint32_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1u;
+}
+
+// Entries always name smaller positions, so a chase ends at a root; the
+// bound check only keeps a corrupted entry from reading outside the map.
+__device__ uint32_t v_find(int32_t* lab, uint32_t r, uint32_t n)
+{
+    while (true) {
+        const uint32_t p = vl_ld(lab + r);
+        if (p == r || p >= n) return r;
+        const uint32_t pp = vl_ld(lab + p);
+        if (pp == p || pp >= n) return p;
+        __hip_atomic_fetch_min(lab + r, (int32_t)(pp + 1u), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        r = pp;
+    }
+}
+
+__device__ void v_union(int32_t* lab, uint32_t a, uint32_t b, uint32_t n)
+{
+    while (true) {
+        a = v_find(lab, a, n);
+        b = v_find(lab, b, n);
+        if (a == b) return;
+        if (a < b) { const uint32_t t = a; a = b; b = t; }
+        const int32_t old = __hip_atomic_fetch_min(lab + a, (int32_t)(b + 1u), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (old == (int32_t)(a + 1u)) return;
+        a = (uint32_t)old - 1u;  // a had been linked meanwhile: unite its parent instead
+    }
+}
+
+__device__ __forceinline__ bool v_fg(const VolArgs& v, int x, int y, int z)
+{
+    return ld_global(v.vol + (int64_t)z * v.slice_pitch + (int64_t)y * v.pitch + x) != 0;
+}
+
+// One thread per voxel of slices 1 .. D-1: unite it with its foreground
+// neighbours in the previous slice.  When the voxel to its left is also
+// foreground it lies in the same slice component and has already united
+// every neighbour in columns x-1 and x, so only column x+1 remains
+// (26-connectivity) or nothing (6-connectivity, when the left neighbour's
+// previous-slice voxel is foreground too).
+template <int C>
+__global__ __launch_bounds__(256) void k_zmerge(VolArgs v)
+{
+    const int64_t S = (int64_t)v.H * v.W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)(v.D - 1) * S) return;
+    const int z = (int)(i / S) + 1;
+    const int64_t rem = i - (int64_t)(z - 1) * S;
+    const int y = (int)(rem / v.W), x = (int)(rem - (int64_t)y * v.W);
+    if (!v_fg(v, x, y, z)) return;
+    const int64_t p = (int64_t)z * S + (int64_t)y * v.W + x;
+    const uint32_t n = (uint32_t)((int64_t)v.D * S);
+    const uint32_t a = vl_ld(v.labels + p);
+    if (a >= n) return;
+    const bool left = x > 0 && v_fg(v, x - 1, y, z);
+    if (C == 6) {
+        if (!v_fg(v, x, y, z - 1)) return;
+        if (left && v_fg(v, x - 1, y, z - 1)) return;
+        const uint32_t b = vl_ld(v.labels + p - S);
+        if (b < n) v_union(v.labels, a, b, n);
+        return;
+    }
+    uint32_t last = 0xffffffffu;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= v.H) continue;
+        for (int dx = left ? 1 : -1; dx <= 1; ++dx) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= v.W || !v_fg(v, xx, yy, z - 1)) continue;
+            const uint32_t b = vl_ld(v.labels + p - S + (int64_t)dy * v.W + dx);
+            if (b == last || b >= n) continue;
+            last = b;
+            v_union(v.labels, a, b, n);
+        }
+    }
+}
+
+// Every foreground voxel takes 1 + its root's position.
+__global__ __launch_bounds__(256) void k_zfinal(VolArgs v)
+{
+    const int64_t n = (int64_t)v.D * v.H * v.W;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t L = ld_global(v.labels + p);
+    if (L == 0) return;
+    uint32_t r = (uint32_t)L - 1u;
+    if ((int64_t)r >= n) return;
+    while (true) {
+        const uint32_t q = vl_ld(v.labels + r);
+        if (q == r || (int64_t)q >= n) break;
+        r = q;
+    }
+    if ((int32_t)(r + 1u) != L) st_global(v.labels + p, (int32_t)(r + 1u));
+}
+
+// ---------------------------------------------------------------------------
 // copy kernel (bandwidth / counter calibration)
 // ---------------------------------------------------------------------------
 
@@ -1884,6 +1997,20 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
     const unsigned fgrid =
         (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<0, false, false>, NT));
     k_final<0, false, false><<<fgrid, NT, 0, st>>>(b, ws, StatsWs{});
+    return hipGetLastError();
+}
+
+hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st)
+{
+    const int64_t S = (int64_t)v.H * v.W, n = (int64_t)v.D * S;
+    if (n == 0) return hipSuccess;
+    if (v.D > 1) {
+        const int64_t m = (int64_t)(v.D - 1) * S;
+        const unsigned g = (unsigned)((m + 255) / 256);
+        if (conn == 26) k_zmerge<26><<<g, 256, 0, st>>>(v);
+        else k_zmerge<6><<<g, 256, 0, st>>>(v);
+        k_zfinal<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(v);
+    }
     return hipGetLastError();
 }
 

@@ -217,3 +217,48 @@ def serving_frames(n: int, seed: int = 0):
     idx = rng.choice(len(SERVING_MIX), size=n, p=w / w.sum())
     return [(SERVING_MIX[i][0], SERVING_MIX[i][1], seed * 1000003 + k)
             for k, i in enumerate(idx)]
+
+
+# ---------------------------------------------------------------------------
+# volumes [z, y, x]
+# ---------------------------------------------------------------------------
+
+def bernoulli3d(D: int, H: int, W: int, p: float, seed: int = 0) -> np.ndarray:
+    rng = rng_for(seed)
+    return (rng.random((D, H, W)) < p).astype(np.uint8)
+
+
+def blobs3d(D: int, H: int, W: int, sigma: float, seed: int = 0,
+            quantile: float = 0.5) -> np.ndarray:
+    """Uniform noise smoothed by a 3-D Gaussian and thresholded at a quantile
+    (coherent regions, like a segmented scan)."""
+    from scipy.ndimage import gaussian_filter
+
+    rng = rng_for(seed)
+    u = rng.random((D, H, W), dtype=np.float32)
+    s = gaussian_filter(u, sigma=sigma, mode="reflect", truncate=4.0)
+    return (s > np.quantile(s, quantile)).astype(np.uint8)
+
+
+def checkerboard3d(D: int, H: int, W: int) -> np.ndarray:
+    z, y, x = np.indices((D, H, W))
+    return ((x + y + z) % 2 == 0).astype(np.uint8)
+
+
+def make3d(kind: str, D: int, H: int, W: int, seed: int = 0, **kw) -> np.ndarray:
+    if kind == "bernoulli":
+        return bernoulli3d(D, H, W, kw.get("p", 0.5), seed)
+    if kind == "blobs":
+        return blobs3d(D, H, W, kw.get("sigma", 2.0), seed, kw.get("quantile", 0.5))
+    if kind == "checkerboard":
+        return checkerboard3d(D, H, W)
+    if kind == "full":
+        return np.ones((D, H, W), np.uint8)
+    if kind == "empty":
+        return np.zeros((D, H, W), np.uint8)
+    if kind == "slabs":  # full even slices, empty odd ones: one component per even slice
+        v = np.zeros((D, H, W), np.uint8)
+        v[::2] = 1
+        return v
+    raise ValueError(kind)
+

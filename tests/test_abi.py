@@ -109,6 +109,29 @@ def test_ablation_validation(lib, args, status):
     assert b"ccl_label_ablation" in lib.ccl_last_error()
 
 
+@pytest.mark.parametrize("args,status", [
+    ((FAKE_IMG, -1, 4, 4, 4, 16, 26, FAKE_OUT), -1),          # negative depth
+    ((FAKE_IMG, 2, 4, 4, 4, 16, 8, FAKE_OUT), -1),            # connectivity 8 is 2-D only
+    ((None, 2, 4, 4, 4, 16, 6, FAKE_OUT), -1),                # null volume
+    ((FAKE_IMG, 2, 4, 4, 4, 16, 6, None), -1),                # null labels
+    ((FAKE_IMG, 2, 4, 8, 7, 32, 6, FAKE_OUT), -1),            # pitch < W
+    ((FAKE_IMG, 2, 4, 4, 4, 8, 26, FAKE_OUT), -1),            # slice pitch < slice
+    ((FAKE_IMG, 2, 4, 4, 4, 16, 26, FAKE_IMG + 8), -1),       # overlap
+    ((FAKE_IMG, 1024, 2048, 2048, 2048, 1 << 22, 26, FAKE_OUT), -2),  # > 2^31 voxels
+    ((FAKE_IMG, 0, 4, 4, 4, 16, 26, FAKE_OUT), 0),            # empty volume
+])
+def test_volume_validation(lib, args, status):
+    f = lib.ccl_label_3d
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                  ctypes.c_void_p]
+    lib.ccl_last_error.restype = ctypes.c_char_p
+    assert f(*args, None) == status
+    if status:
+        assert b"ccl_label_3d" in lib.ccl_last_error()
+
+
 def test_batch_validation(lib):
     import paper_1712_09789_amd.ccl as c  # the binding loads on CPU too
     descs = (c.ImageDesc * 3)()

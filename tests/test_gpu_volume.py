@@ -1,0 +1,76 @@
+"""Volumes through ccl_label_3d against the 3-D oracle, element by element
+(tolerance 0), for 6- and 26-connectivity."""
+import numpy as np
+import pytest
+
+from oracle import oracle_label3d
+from paper_1712_09789_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ccl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1712_09789_amd.ccl as c
+    return c
+
+
+def check(ccl, vol, conn, what="", dev=None):
+    print(f"[volume] {what} {vol.shape} conn={conn}", flush=True)
+    d = torch.from_numpy(np.ascontiguousarray(vol)).cuda() if dev is None else dev
+    got = ccl.label_3d(d, conn)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    want = oracle_label3d(vol, conn)
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        z, y, x = bad[0]
+        raise AssertionError(f"{what} {vol.shape} conn={conn}: {len(bad)} mismatches, first at "
+                             f"({z},{y},{x}) got {got[z, y, x]} want {want[z, y, x]}")
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 5), (3, 64, 64), (5, 65, 63),
+                                   (4, 130, 70), (17, 100, 120), (40, 20, 300)])
+@pytest.mark.parametrize("p", [0.2, 0.5])
+def test_random_shapes(ccl, shape, p, conn):
+    check(ccl, wl.bernoulli3d(*shape, p, seed=sum(shape)), conn, f"bernoulli{p}")
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+@pytest.mark.parametrize("kind,kw", [("blobs", {"sigma": 2.0}), ("blobs", {"sigma": 4.0}),
+                                     ("checkerboard", {}), ("full", {}), ("empty", {}),
+                                     ("slabs", {}), ("bernoulli", {"p": 0.3})])
+def test_contents_64x128x128(ccl, kind, kw, conn):
+    check(ccl, wl.make3d(kind, 64, 128, 128, seed=1, **kw), conn, f"{kind}{kw}")
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_strided_volume(ccl, conn):
+    big = wl.bernoulli3d(12, 70, 90, 0.45, seed=4)
+    dbig = torch.from_numpy(big).cuda()
+    view = dbig[1:11, 3:60, 5:85]  # rows and slices pitched wider than the view
+    check(ccl, big[1:11, 3:60, 5:85], conn, "strided", dev=view)
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_bench_size_128(ccl, conn):
+    for kind, kw in (("bernoulli", {"p": 0.5}), ("blobs", {"sigma": 2.0})):
+        check(ccl, wl.make3d(kind, 128, 128, 128, seed=0, **kw), conn, f"128^3 {kind}{kw}")
+
+
+def test_repeated_volume_labelling(ccl):
+    # the merge across slices races on the label map; many repetitions
+    vol = wl.bernoulli3d(64, 96, 96, 0.35, seed=9)
+    d = torch.from_numpy(vol).cuda()
+    want = {c: oracle_label3d(vol, c) for c in (6, 26)}
+    out = torch.empty(vol.shape, dtype=torch.int32, device="cuda")
+    for rep in range(20):
+        for c in (6, 26):
+            ccl.label_3d(d, c, out=out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want[c]), (rep, c)
