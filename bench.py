@@ -383,6 +383,53 @@ def bench_ablation(ccl, torch, dev, check=True):
     return out
 
 
+def bench_volume(ccl, torch, dev, check=True, n=512, reps=10):
+    """ccl_label_3d on n^3 volumes (Bernoulli p = 0.3 / 0.5, 3-D blobs sigma
+    2 thresholded at the median) under 6- and 26-connectivity, in
+    Gvoxel/s; exactness against the 3-D oracle on 192^3 volumes of the same
+    kinds, whose one-core rate is the CPU baseline."""
+    from paper_1712_09789_amd import workloads as wl
+    kinds = (("bernoulli", {"p": 0.3}), ("bernoulli", {"p": 0.5}), ("blobs", {"sigma": 2.0}))
+    out = {"size": n}
+    st = torch.cuda.current_stream()
+    lab = torch.empty((n, n, n), dtype=torch.int32, device=dev)
+    for kind, kw in kinds:
+        vol = torch.from_numpy(wl.make3d(kind, n, n, n, seed=0, **kw)).to(dev)
+        for conn in (6, 26):
+            ccl.label_3d(vol, conn, out=lab)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                ccl.label_3d(vol, conn, out=lab)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            out[f"{kind}{kw} conn={conn}"] = {"Gvox/s": round(n ** 3 / ms / 1e6, 1),
+                                              "us": round(1e3 * ms, 1)}
+        del vol
+    del lab
+    torch.cuda.empty_cache()
+    if check:
+        import oracle
+        m = 192
+        exact, cpu_secs = True, 0.0
+        for kind, kw in kinds:
+            vol = wl.make3d(kind, m, m, m, seed=1, **kw)
+            d = torch.from_numpy(vol).to(dev)
+            for conn in (6, 26):
+                got = ccl.label_3d(d, conn).cpu().numpy()
+                c0 = time.perf_counter()
+                want = oracle.oracle_label3d(vol, conn)
+                cpu_secs += time.perf_counter() - c0
+                exact &= bool(np.array_equal(got, want))
+        out["exact_sampled"] = exact
+        out["cpu_baseline"] = {"value": round(6 * m ** 3 / cpu_secs / 1e9, 5),
+                               "unit": "Gvoxel/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the three kinds at {m}^3, both connectivities, once"}
+    return out
+
+
 def bench_batch(ccl, torch, dev, check=True, n=256, reps=5):
     """256 uint8 images, sides log-uniform in [64, 2048], half Bernoulli and
     half blobs at random density, 8-connectivity: one ccl_label_batch call
@@ -690,6 +737,8 @@ def main():
         result["stats_4096"] = bench_stats(ccl, torch, dev, cases, devs, 1e3 * ms_step,
                                            min(args.steps, 140), check=cpu is not None)
         log(f"[bench] stats: {result['stats_4096']}")
+        result["volume_512"] = bench_volume(ccl, torch, dev, check=cpu is not None)
+        log(f"[bench] volume: {result['volume_512']}")
         result["ablation"] = bench_ablation(ccl, torch, dev, check=cpu is not None)
         log(f"[bench] ablation: {result['ablation']['time_4096_us']} exact {result['ablation']['exact']}")
         result["batch_256"] = bench_batch(ccl, torch, dev, check=cpu is not None)

@@ -1791,27 +1791,46 @@ __device__ __forceinline__ bool v_fg(const VolArgs& v, int x, int y, int z)
 // foreground it lies in the same slice component and has already united
 // every neighbour in columns x-1 and x, so only column x+1 remains
 // (26-connectivity) or nothing (6-connectivity, when the left neighbour's
-// previous-slice voxel is foreground too).
+// previous-slice voxel is foreground too).  A workgroup takes a 16 x 16
+// square of one slice pair, and pairs of entries another of its threads
+// already holds are dropped (LDS hash, as in k_seam): inside a square most
+// voxels join the same few slice components.
+constexpr int ZM_HASH = 512;
+constexpr int ZM_SIDE = 16;  // square side; ZM_SIDE^2 threads per workgroup
 template <int C>
-__global__ __launch_bounds__(256) void k_zmerge(VolArgs v)
+__global__ __launch_bounds__(ZM_SIDE * ZM_SIDE) void k_zmerge(VolArgs v, int sqx, int sqy)
 {
+    __shared__ unsigned long long seen[ZM_HASH];
+    for (int k = threadIdx.x; k < ZM_HASH; k += blockDim.x) seen[k] = ~0ull;
+    __syncthreads();
     const int64_t S = (int64_t)v.H * v.W;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)(v.D - 1) * S) return;
-    const int z = (int)(i / S) + 1;
-    const int64_t rem = i - (int64_t)(z - 1) * S;
-    const int y = (int)(rem / v.W), x = (int)(rem - (int64_t)y * v.W);
-    if (!v_fg(v, x, y, z)) return;
-    const int64_t p = (int64_t)z * S + (int64_t)y * v.W + x;
     const uint32_t n = (uint32_t)((int64_t)v.D * S);
+    const int64_t sq = blockIdx.x;  // square index over (slice 1 .. D-1, square row, column)
+    const int64_t per_slice = (int64_t)sqx * sqy;
+    const int z = (int)(sq / per_slice) + 1;
+    const int r = (int)(sq - (int64_t)(z - 1) * per_slice);
+    const int x = (r % sqx) * ZM_SIDE + (int)(threadIdx.x % ZM_SIDE);
+    const int y = (r / sqx) * ZM_SIDE + (int)(threadIdx.x / ZM_SIDE);
+    if (x >= v.W || y >= v.H || !v_fg(v, x, y, z)) return;
+    const int64_t p = (int64_t)z * S + (int64_t)y * v.W + x;
     const uint32_t a = vl_ld(v.labels + p);
     if (a >= n) return;
+    auto unite = [&](uint32_t b) {
+        if (b >= n || b == a) return;
+        const unsigned long long key = ((unsigned long long)a << 32) | b;
+        uint32_t h = (a * 0x9e3779b1u) ^ (b * 0x85ebca77u);
+        for (int probe = 0; probe < 8; ++probe, ++h) {
+            const unsigned long long prev = atomicCAS(seen + (h & (ZM_HASH - 1)), ~0ull, key);
+            if (prev == key) return;   // another thread of the workgroup unites this pair
+            if (prev == ~0ull) break;  // claimed a fresh entry
+        }
+        v_union(v.labels, a, b, n);
+    };
     const bool left = x > 0 && v_fg(v, x - 1, y, z);
     if (C == 6) {
         if (!v_fg(v, x, y, z - 1)) return;
         if (left && v_fg(v, x - 1, y, z - 1)) return;
-        const uint32_t b = vl_ld(v.labels + p - S);
-        if (b < n) v_union(v.labels, a, b, n);
+        unite(vl_ld(v.labels + p - S));
         return;
     }
     uint32_t last = 0xffffffffu;
@@ -1822,9 +1841,9 @@ __global__ __launch_bounds__(256) void k_zmerge(VolArgs v)
             const int xx = x + dx;
             if (xx < 0 || xx >= v.W || !v_fg(v, xx, yy, z - 1)) continue;
             const uint32_t b = vl_ld(v.labels + p - S + (int64_t)dy * v.W + dx);
-            if (b == last || b >= n) continue;
+            if (b == last) continue;
             last = b;
-            v_union(v.labels, a, b, n);
+            unite(b);
         }
     }
 }
@@ -2005,10 +2024,10 @@ hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st)
     const int64_t S = (int64_t)v.H * v.W, n = (int64_t)v.D * S;
     if (n == 0) return hipSuccess;
     if (v.D > 1) {
-        const int64_t m = (int64_t)(v.D - 1) * S;
-        const unsigned g = (unsigned)((m + 255) / 256);
-        if (conn == 26) k_zmerge<26><<<g, 256, 0, st>>>(v);
-        else k_zmerge<6><<<g, 256, 0, st>>>(v);
+        const int sqx = (v.W + ZM_SIDE - 1) / ZM_SIDE, sqy = (v.H + ZM_SIDE - 1) / ZM_SIDE;
+        const unsigned g = (unsigned)((int64_t)(v.D - 1) * sqx * sqy);
+        if (conn == 26) k_zmerge<26><<<g, ZM_SIDE * ZM_SIDE, 0, st>>>(v, sqx, sqy);
+        else k_zmerge<6><<<g, ZM_SIDE * ZM_SIDE, 0, st>>>(v, sqx, sqy);
         k_zfinal<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(v);
     }
     return hipGetLastError();
