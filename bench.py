@@ -556,6 +556,9 @@ def main():
     ap.add_argument("--profile-stats", type=int, default=0, metavar="ROUNDS",
                     help="only run ccl_label_stats over the headline images ROUNDS times "
                          "(for a kernel trace of the statistics path) and exit")
+    ap.add_argument("--profile-volume", type=int, default=0, metavar="ROUNDS",
+                    help="only run ccl_label_3d on the 512^3 Bernoulli p = 0.3 volume, both "
+                         "connectivities, ROUNDS times (for a kernel trace) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel over MIB MiB (counter calibration)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"),
@@ -602,6 +605,18 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": n,
                           "avg_us": 1e3 * ms / n,
                           "read_plus_write_GBs": 2 * nbytes / (ms / n / 1e3) / 1e9}))
+        return
+
+    if args.profile_volume:
+        from paper_1712_09789_amd import workloads as wl
+        n = 512
+        vol = torch.from_numpy(wl.make3d("bernoulli", n, n, n, seed=0, p=0.3)).to(dev)
+        lab = torch.empty((n, n, n), dtype=torch.int32, device=dev)
+        for _ in range(args.profile_volume):
+            for conn in (6, 26):
+                ccl.label_3d(vol, conn, out=lab)
+        torch.cuda.synchronize()
+        log(f"[bench] profile-volume: {args.profile_volume} rounds")
         return
 
     size = args.size
