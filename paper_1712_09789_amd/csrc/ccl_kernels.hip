@@ -1057,10 +1057,20 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
     // root after the block merge); before any merge the node is the root.
     if (f.node >= 0) {
         if (!LOCAL_ONLY) {
+            // The merge is over, so every node's root is fixed and any
+            // ancestor is a valid parent: beyond the first hop (whose node
+            // the whole group's tiles share) the path is halved with plain
+            // stores, which keeps later chases short on images whose merge
+            // left long chains (one component snaking through many groups).
             uint32_t n = (uint32_t)f.node;
+            bool first = true;
             while ((uint32_t)v != n) {
-                n = (uint32_t)v;
-                v = ws.forest[n];
+                const uint32_t p = (uint32_t)v;
+                const uint64_t vp = ld_global(ws.forest + p);
+                if (!first && (uint32_t)vp != p) st_global(ws.forest + n, vp);
+                first = false;
+                n = p;
+                v = vp;
             }
         }
         sh.fin[tid] = (int32_t)((uint32_t)(v >> 32) + 1u) + a.lbase;
