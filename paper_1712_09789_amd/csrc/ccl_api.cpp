@@ -407,13 +407,11 @@ int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pi
     int rc = run_batch(slices, conn2, st, false, who);
     if (rc != CCL_OK) return rc;
     VolArgs v;
-    v.vol = vol;
-    v.pitch = pitch_bytes;
-    v.slice_pitch = slice_pitch_bytes;
     v.labels = labels;
     v.D = D;
     v.H = H;
     v.W = W;
+    v.vec = ((uintptr_t)labels & 15) == 0;
     hipError_t e = launch_volume(v, connectivity, st);
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
     return CCL_OK;

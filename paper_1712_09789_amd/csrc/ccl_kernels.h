@@ -33,12 +33,12 @@ struct ImageArgs {
 static_assert(sizeof(ImageArgs) == 64, "ImageArgs is one 64-byte scalar load");
 
 // A volume whose slices were labelled as a batch of images (labels lifted to
-// voxel positions by lbase).
+// voxel positions by lbase); the labels alone carry what the merge across
+// slices needs (nonzero exactly on foreground).
 struct VolArgs {
-    const uint8_t* vol;
-    int64_t pitch, slice_pitch;  // bytes between rows / slices
-    int32_t* labels;             // dense D x H x W
+    int32_t* labels;  // dense D x H x W
     int32_t D, H, W;
+    int32_t vec;      // labels is 16-byte aligned
 };
 
 // Images labelled by one set of launches (all of one connectivity).  With n

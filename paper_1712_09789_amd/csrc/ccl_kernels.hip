@@ -178,6 +178,48 @@ __device__ void punion(uint32_t* P, uint32_t a, uint32_t b)
     }
 }
 
+// Caller buffers (image, labels, statistics) are reached through pointers
+// read from memory, which the compiler cannot place in an address space, so
+// it would use flat instructions; flat accesses also count against the LDS
+// wait counter, and every LDS wait would then wait for them too (the
+// next-tile prefetch and the label stores included).  These accessors name
+// the global address space explicitly.
+template <typename V>
+__device__ __forceinline__ V ld_global(const V* p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(1))) V*)p;
+#else
+    return *p;  // host pass: never executed
+#endif
+}
+template <typename V>
+__device__ __forceinline__ void st_global(V* p, const V& v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    *(__attribute__((address_space(1))) V*)p = v;
+#else
+    *p = v;  // host pass: never executed
+#endif
+}
+// 16-byte accesses go through plain vector types: the copy of HIP's uint4 /
+// int4 classes would turn the global lvalue back into a generic one.
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_global16(const void* p)
+{
+    const v4u32 v = ld_global(reinterpret_cast<const v4u32*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_global16(void* p, int32_t a, int32_t b, int32_t c, int32_t d)
+{
+    v4u32 v;
+    v.x = (uint32_t)a;
+    v.y = (uint32_t)b;
+    v.z = (uint32_t)c;
+    v.w = (uint32_t)d;
+    st_global(reinterpret_cast<v4u32*>(p), v);
+}
+
 // ---------------------------------------------------------------------------
 // HBM forest over border components.  Entry = (key of parent << 32) | parent
 // node; a root stores its own key and id.  Keys (raster position of a tile
@@ -195,19 +237,30 @@ __device__ __forceinline__ uint64_t g_ld(const uint64_t* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Reads of the forest during a merge.  A find's first two hops use plain
+// (cacheable) loads: most finds end there, at a root many threads share.  A
+// stale entry still names an ancestor, and a stale "root" is caught by the
+// link's atomic min, which returns the current entry, and the union goes on
+// from there; longer chases switch to coherent loads, which keep chains that
+// are being rewritten from being walked through old entries.
+__device__ __forceinline__ uint64_t g_hop(const uint64_t* p, int step)
+{
+    return step < 2 ? ld_global(p) : g_ld(p);
+}
+
 // Root of n, given v = F[n] already loaded.  Halves the path on the way
 // (an atomic min, so a concurrent link to a smaller key is never undone).
 __device__ Root g_find_from(uint64_t* F, uint32_t n, uint64_t v)
 {
-    while (true) {
+    for (int step = 0;; step += 2) {
         uint32_t p = (uint32_t)v;
         if (p == n) return Root{n, (uint32_t)(v >> 32)};
-        uint64_t vp = g_ld(F + p);
+        uint64_t vp = g_hop(F + p, step);
         uint32_t pp = (uint32_t)vp;
         if (pp == p) return Root{p, (uint32_t)(vp >> 32)};
         __hip_atomic_fetch_min(F + n, vp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         n = pp;
-        v = g_ld(F + n);
+        v = g_hop(F + n, step + 1);
     }
 }
 
@@ -217,7 +270,7 @@ __device__ Root g_find_from(uint64_t* F, uint32_t n, uint64_t v)
 __device__ void g_union(uint64_t* F, uint32_t a, uint32_t b)
 {
     while (true) {
-        const uint64_t va = g_ld(F + a), vb = g_ld(F + b);
+        const uint64_t va = g_hop(F + a, 0), vb = g_hop(F + b, 0);
         Root ra = g_find_from(F, a, va);
         Root rb = g_find_from(F, b, vb);
         if (ra.node == rb.node) return;
@@ -360,48 +413,6 @@ __device__ __forceinline__ V ld_uniform(const V* p)
 #else
     return *p;  // host pass: never executed
 #endif
-}
-
-// Caller buffers (image, labels, statistics) are reached through pointers
-// read from memory, which the compiler cannot place in an address space, so
-// it would use flat instructions; flat accesses also count against the LDS
-// wait counter, and every LDS wait would then wait for them too (the
-// next-tile prefetch and the label stores included).  These accessors name
-// the global address space explicitly.
-template <typename V>
-__device__ __forceinline__ V ld_global(const V* p)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return *(const __attribute__((address_space(1))) V*)p;
-#else
-    return *p;  // host pass: never executed
-#endif
-}
-template <typename V>
-__device__ __forceinline__ void st_global(V* p, const V& v)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    *(__attribute__((address_space(1))) V*)p = v;
-#else
-    *p = v;  // host pass: never executed
-#endif
-}
-// 16-byte accesses go through plain vector types: the copy of HIP's uint4 /
-// int4 classes would turn the global lvalue back into a generic one.
-typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ uint4 ld_global16(const void* p)
-{
-    const v4u32 v = ld_global(reinterpret_cast<const v4u32*>(p));
-    return make_uint4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void st_global16(void* p, int32_t a, int32_t b, int32_t c, int32_t d)
-{
-    v4u32 v;
-    v.x = (uint32_t)a;
-    v.y = (uint32_t)b;
-    v.z = (uint32_t)c;
-    v.w = (uint32_t)d;
-    st_global(reinterpret_cast<v4u32*>(p), v);
 }
 
 __device__ __forceinline__ ImageArgs batch_image(const BatchArgs& b, int i)
@@ -1757,19 +1768,23 @@ __global__ __launch_bounds__(NT) void k_local_ablate(BatchArgs b, Workspace ws, 
 // voxel of each slice component starts as a root, and a merge points the
 // larger root at the smaller with an atomic min, so entries only decrease.
 
-__device__ __forceinline__ uint32_t vl_ld(const int32_t* p)
+// Entry of a node during the merge: the first two hops of a find use plain
+// loads, later ones coherent loads (as g_hop for the 2-D forest).
+__device__ __forceinline__ uint32_t vl_hop(const int32_t* p, int step)
 {
-    return (uint32_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1u;
+    return (uint32_t)(step < 2 ? ld_global(p)
+                               : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) -
+           1u;
 }
 
 // Entries always name smaller positions, so a chase ends at a root; the
 // bound check only keeps a corrupted entry from reading outside the map.
 __device__ uint32_t v_find(int32_t* lab, uint32_t r, uint32_t n)
 {
-    while (true) {
-        const uint32_t p = vl_ld(lab + r);
+    for (int step = 0;; step += 2) {
+        const uint32_t p = vl_hop(lab + r, step);
         if (p == r || p >= n) return r;
-        const uint32_t pp = vl_ld(lab + p);
+        const uint32_t pp = vl_hop(lab + p, step + 1);
         if (pp == p || pp >= n) return p;
         __hip_atomic_fetch_min(lab + r, (int32_t)(pp + 1u), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -1787,93 +1802,154 @@ __device__ void v_union(int32_t* lab, uint32_t a, uint32_t b, uint32_t n)
         const int32_t old = __hip_atomic_fetch_min(lab + a, (int32_t)(b + 1u), __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
         if (old == (int32_t)(a + 1u)) return;
-        a = (uint32_t)old - 1u;  // a had been linked meanwhile: unite its parent instead
+        a = (uint32_t)old - 1u;  // a was no root (linked meanwhile, or read stale): go on from its parent
     }
 }
 
-__device__ __forceinline__ bool v_fg(const VolArgs& v, int x, int y, int z)
+// k_zmerge: one workgroup per 64 x 16 block of a slice pair (z-1, z).  The
+// block's labels in both slices are staged in LDS with one 64-bit foreground
+// mask per row (a label is nonzero exactly on foreground); slice z-1 gets a
+// rim of one row and one column, which 26-connectivity reaches.  The work is
+// done per run: each maximal stretch of foreground in a block row of slice z
+// lies in one slice component, so one label names it, and it is united with
+// every run of slice z-1 it touches (again one label each): the run directly
+// below for 6-connectivity; for 26 the runs in the three rows around it, one
+// column further on each side, the rim included.  A run that crosses the
+// block's edge is cut there; the two parts together touch the same runs.  A
+// thread drops a pair equal to the one it united last, and the workgroup
+// drops pairs another of its threads already holds (LDS hash, as in k_seam).
+// The staged labels may be stale (roots are lowered meanwhile): any
+// ancestor of a component serves.
+constexpr int ZB_W = 64, ZB_H = 16;  // block of a slice pair
+constexpr int ZM_HASH = 1024;
+__device__ __forceinline__ uint64_t bit_range(int lo, int hi)  // bits lo .. hi, 0 <= lo <= hi <= 63
 {
-    return ld_global(v.vol + (int64_t)z * v.slice_pitch + (int64_t)y * v.pitch + x) != 0;
+    return (~0ull >> (63 - hi)) & (~0ull << lo);
 }
-
-// One thread per voxel of slices 1 .. D-1: unite it with its foreground
-// neighbours in the previous slice.  When the voxel to its left is also
-// foreground it lies in the same slice component and has already united
-// every neighbour in columns x-1 and x, so only column x+1 remains
-// (26-connectivity) or nothing (6-connectivity, when the left neighbour's
-// previous-slice voxel is foreground too).  A workgroup takes a 16 x 16
-// square of one slice pair, and pairs of entries another of its threads
-// already holds are dropped (LDS hash, as in k_seam): inside a square most
-// voxels join the same few slice components.
-constexpr int ZM_HASH = 512;
-constexpr int ZM_SIDE = 16;  // square side; ZM_SIDE^2 threads per workgroup
 template <int C>
-__global__ __launch_bounds__(ZM_SIDE * ZM_SIDE) void k_zmerge(VolArgs v, int sqx, int sqy)
+__global__ __launch_bounds__(256) void k_zmerge(VolArgs v, int nbx, int nby)
 {
+    static_assert(ZB_W == 64 && ZB_H * 16 == 256, "a wave per staged row; 16 threads per block row");
+    constexpr int PR = ZB_H + 2;                 // staged rows of slice z-1: y0-1 .. y0+ZB_H
+    __shared__ int32_t plab[PR][ZB_W + 2];       // slice z-1, columns x0-1 .. x0+ZB_W
+    __shared__ int32_t clab[ZB_H][ZB_W];         // slice z, columns x0 .. x0+ZB_W-1
+    __shared__ uint64_t pm[PR], cm[ZB_H];        // foreground of columns x0 .. x0+63
     __shared__ unsigned long long seen[ZM_HASH];
-    for (int k = threadIdx.x; k < ZM_HASH; k += blockDim.x) seen[k] = ~0ull;
-    __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = tid; k < ZM_HASH; k += 256) seen[k] = ~0ull;
     const int64_t S = (int64_t)v.H * v.W;
     const uint32_t n = (uint32_t)((int64_t)v.D * S);
-    const int64_t sq = blockIdx.x;  // square index over (slice 1 .. D-1, square row, column)
-    const int64_t per_slice = (int64_t)sqx * sqy;
-    const int z = (int)(sq / per_slice) + 1;
-    const int r = (int)(sq - (int64_t)(z - 1) * per_slice);
-    const int x = (r % sqx) * ZM_SIDE + (int)(threadIdx.x % ZM_SIDE);
-    const int y = (r / sqx) * ZM_SIDE + (int)(threadIdx.x / ZM_SIDE);
-    if (x >= v.W || y >= v.H || !v_fg(v, x, y, z)) return;
-    const int64_t p = (int64_t)z * S + (int64_t)y * v.W + x;
-    const uint32_t a = vl_ld(v.labels + p);
-    if (a >= n) return;
-    auto unite = [&](uint32_t b) {
-        if (b >= n || b == a) return;
+    const int64_t per_slice = (int64_t)nbx * nby;
+    const int z = (int)(blockIdx.x / per_slice) + 1;
+    const int r = (int)(blockIdx.x - (int64_t)(z - 1) * per_slice);
+    const int x0 = (r % nbx) * ZB_W, y0 = (r / nbx) * ZB_H;
+    const int32_t* Lp = v.labels + (int64_t)(z - 1) * S;
+    const int32_t* Lc = v.labels + (int64_t)z * S;
+    // one staged row per wave step, one column per lane (wave-uniform loop)
+    for (int row = wave; row < PR + ZB_H; row += 4) {
+        const bool prev = row < PR;
+        if (C == 6 && (row == 0 || row == PR - 1)) continue;  // rim rows: 26 only
+        const int y = prev ? y0 - 1 + row : y0 + (row - PR);
+        const int x = x0 + lane;
+        int32_t val = 0;
+        if (y >= 0 && y < v.H && x < v.W) val = ld_global((prev ? Lp : Lc) + (int64_t)y * v.W + x);
+        const uint64_t m = __ballot(val != 0);
+        if (prev) {
+            plab[row][lane + 1] = val;
+            if (lane == 0) pm[row] = m;
+        } else {
+            clab[row - PR][lane] = val;
+            if (lane == 0) cm[row - PR] = m;
+        }
+    }
+    if (C == 26 && tid < 2 * PR) {  // rim columns x0-1 and x0+64 of slice z-1
+        const int row = tid >> 1, side = tid & 1;
+        const int y = y0 - 1 + row, x = side ? x0 + ZB_W : x0 - 1;
+        plab[row][side ? ZB_W + 1 : 0] =
+            (y >= 0 && y < v.H && x >= 0 && x < v.W) ? ld_global(Lp + (int64_t)y * v.W + x) : 0;
+    }
+    __syncthreads();
+    uint32_t la = ~0u, lb = ~0u;  // the pair this thread united last
+    auto unite = [&](uint32_t a, int32_t B) {
+        const uint32_t b = (uint32_t)B - 1u;
+        if (a >= n || b >= n || a == b || (a == la && b == lb)) return;
+        la = a;
+        lb = b;
         const unsigned long long key = ((unsigned long long)a << 32) | b;
         uint32_t h = (a * 0x9e3779b1u) ^ (b * 0x85ebca77u);
         for (int probe = 0; probe < 8; ++probe, ++h) {
-            const unsigned long long prev = atomicCAS(seen + (h & (ZM_HASH - 1)), ~0ull, key);
-            if (prev == key) return;   // another thread of the workgroup unites this pair
-            if (prev == ~0ull) break;  // claimed a fresh entry
+            const unsigned long long old = atomicCAS(seen + (h & (ZM_HASH - 1)), ~0ull, key);
+            if (old == key) return;   // another thread of the workgroup unites this pair
+            if (old == ~0ull) break;  // claimed a fresh entry
         }
         v_union(v.labels, a, b, n);
     };
-    const bool left = x > 0 && v_fg(v, x - 1, y, z);
-    if (C == 6) {
-        if (!v_fg(v, x, y, z - 1)) return;
-        if (left && v_fg(v, x - 1, y, z - 1)) return;
-        unite(vl_ld(v.labels + p - S));
-        return;
-    }
-    uint32_t last = 0xffffffffu;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = y + dy;
-        if (yy < 0 || yy >= v.H) continue;
-        for (int dx = left ? 1 : -1; dx <= 1; ++dx) {
-            const int xx = x + dx;
-            if (xx < 0 || xx >= v.W || !v_fg(v, xx, yy, z - 1)) continue;
-            const uint32_t b = vl_ld(v.labels + p - S + (int64_t)dy * v.W + dx);
-            if (b == last) continue;
-            last = b;
-            unite(b);
+    // thread: block row ty, runs starting in columns c0 .. c0+3
+    const int ty = tid >> 4, c0 = (tid & 15) * 4;
+    const uint64_t m = cm[ty];
+    uint64_t starts = m & ~(m << 1) & (0xfull << c0);
+    while (starts) {
+        const int c = __builtin_ctzll(starts);
+        starts &= starts - 1;
+        const uint64_t rest = ~m >> c;  // bit 0 clear: column c is foreground
+        const int e = rest ? c + __builtin_ctzll(rest) - 1 : 63;
+        const uint32_t a = (uint32_t)clab[ty][c] - 1u;
+        const int lo = C == 26 ? c - 1 : c, hi = C == 26 ? e + 1 : e;  // columns touched
+        for (int pr = C == 26 ? ty : ty + 1; pr <= (C == 26 ? ty + 2 : ty + 1); ++pr) {
+            const uint64_t q = pm[pr] & bit_range(lo < 0 ? 0 : lo, hi > 63 ? 63 : hi);
+            for (uint64_t s2 = q & ~(q << 1); s2; s2 &= s2 - 1)
+                unite(a, plab[pr][__builtin_ctzll(s2) + 1]);
+            // rim voxels, unless the run through column 0 / 63 already reached them
+            if (lo < 0 && !(q & 1ull) && plab[pr][0] != 0) unite(a, plab[pr][0]);
+            if (hi > 63 && !(q >> 63) && plab[pr][ZB_W + 1] != 0) unite(a, plab[pr][ZB_W + 1]);
         }
     }
 }
 
-// Every foreground voxel takes 1 + its root's position.
+// Every foreground voxel takes 1 + its root's position; four consecutive
+// voxels per thread, and a label equal to the previous voxel's reuses its
+// root.  The merge is over, so every entry read is an ancestor whatever this
+// kernel has already rewritten, and roots are never rewritten.
 __global__ __launch_bounds__(256) void k_zfinal(VolArgs v)
 {
     const int64_t n = (int64_t)v.D * v.H * v.W;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t L = ld_global(v.labels + p);
-    if (L == 0) return;
-    uint32_t r = (uint32_t)L - 1u;
-    if ((int64_t)r >= n) return;
-    while (true) {
-        const uint32_t q = vl_ld(v.labels + r);
-        if (q == r || (int64_t)q >= n) break;
-        r = q;
+    const int64_t q = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= n) return;
+    const bool whole = v.vec && q + 4 <= n;
+    int32_t L[4];
+    if (whole) {
+        const uint4 w = ld_global16(v.labels + q);
+        L[0] = (int32_t)w.x; L[1] = (int32_t)w.y; L[2] = (int32_t)w.z; L[3] = (int32_t)w.w;
+    } else {
+        for (int i = 0; i < 4; ++i) L[i] = q + i < n ? ld_global(v.labels + q + i) : 0;
     }
-    if ((int32_t)(r + 1u) != L) st_global(v.labels + p, (int32_t)(r + 1u));
+    int32_t o[4];
+    int32_t lastL = 0, lastR = 0;
+    bool changed = false;
+    for (int i = 0; i < 4; ++i) {
+        o[i] = L[i];
+        if (L[i] == 0) continue;
+        if (L[i] != lastL) {
+            uint32_t r = (uint32_t)L[i] - 1u;
+            if ((int64_t)r >= n) continue;
+            while (true) {
+                const uint32_t p = (uint32_t)ld_global(v.labels + r) - 1u;
+                if (p == r || (int64_t)p >= n) break;
+                r = p;
+            }
+            lastL = L[i];
+            lastR = (int32_t)(r + 1u);
+        }
+        o[i] = lastR;
+        changed |= o[i] != L[i];
+    }
+    if (!changed) return;
+    if (whole) {
+        st_global16(v.labels + q, o[0], o[1], o[2], o[3]);
+    } else {
+        for (int i = 0; i < 4; ++i)
+            if (q + i < n && o[i] != L[i]) st_global(v.labels + q + i, o[i]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2034,11 +2110,11 @@ hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st)
     const int64_t S = (int64_t)v.H * v.W, n = (int64_t)v.D * S;
     if (n == 0) return hipSuccess;
     if (v.D > 1) {
-        const int sqx = (v.W + ZM_SIDE - 1) / ZM_SIDE, sqy = (v.H + ZM_SIDE - 1) / ZM_SIDE;
-        const unsigned g = (unsigned)((int64_t)(v.D - 1) * sqx * sqy);
-        if (conn == 26) k_zmerge<26><<<g, ZM_SIDE * ZM_SIDE, 0, st>>>(v, sqx, sqy);
-        else k_zmerge<6><<<g, ZM_SIDE * ZM_SIDE, 0, st>>>(v, sqx, sqy);
-        k_zfinal<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(v);
+        const int nbx = (v.W + ZB_W - 1) / ZB_W, nby = (v.H + ZB_H - 1) / ZB_H;
+        const unsigned g = (unsigned)((int64_t)(v.D - 1) * nbx * nby);
+        if (conn == 26) k_zmerge<26><<<g, 256, 0, st>>>(v, nbx, nby);
+        else k_zmerge<6><<<g, 256, 0, st>>>(v, nbx, nby);
+        k_zfinal<<<(unsigned)((n / 4 + 256) / 256), 256, 0, st>>>(v);
     }
     return hipGetLastError();
 }
