@@ -74,3 +74,31 @@ def test_repeated_volume_labelling(ccl):
             ccl.label_3d(d, c, out=out)
             torch.cuda.synchronize()
             assert np.array_equal(out.cpu().numpy(), want[c]), (rep, c)
+
+
+def _edge_patterns():
+    """Volumes whose slice-to-slice contacts sit on the 64 x 16 blocks' edges
+    and rims: diagonal lines of single voxels (26-connected only) crossing
+    columns 63/64 and rows 15/16, rows that alternate between y = 15 and 16
+    from slice to slice, and columns that alternate between x = 63 and 64."""
+    D, H, W = 24, 40, 200
+    diag = np.zeros((D, H, W), np.uint8)
+    for z in range(D):
+        for y0, x0, sx in ((2, 50, 1), (5, 70, -1), (0, 120, 1), (10, 190, -1)):
+            y, x = y0 + z, x0 + sx * z
+            if 0 <= y < H and 0 <= x < W:
+                diag[z, y, x] = 1
+    rows = np.zeros((D, H, W), np.uint8)
+    cols = np.zeros((D, H, W), np.uint8)
+    for z in range(D):
+        rows[z, 15 + (z & 1), 3:197] = 1
+        rows[z, 31 + (z & 1), 60:70] = 1
+        cols[z, 2:38, 63 + (z & 1)] = 1
+        cols[z, 5:9, 127 + (z & 1)] = 1
+    return {"diagonals": diag, "rows": rows, "cols": cols}
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+@pytest.mark.parametrize("name", ["diagonals", "rows", "cols"])
+def test_block_edge_contacts(ccl, name, conn):
+    check(ccl, _edge_patterns()[name], conn, name)
