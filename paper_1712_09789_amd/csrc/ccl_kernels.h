@@ -112,8 +112,8 @@ struct StatRec {
     int32_t area, x_min, x_max, y_min, y_max;
     int64_t sum_x, sum_y;
 };
-constexpr int MERGE_FAN = 4;     // a merge workgroup takes 4 x 4 parts of the level below
-constexpr int MERGE_HT = 2048;   // its hash table: distinct components, and records out
+constexpr int MERGE_FAN = 4;     // a merge workgroup takes the records of 4 x 4 tiles
+constexpr int MERGE_HT = 2048;   // its hash table of distinct components
 
 struct StatsWs {
     uint64_t* rootbits;  // [ntiles][TILE_ROWS] smallest pixels of components, by tile row
@@ -122,10 +122,8 @@ struct StatsWs {
     uint32_t* boff;      // [nblk] exclusive scan of bsum
     StatRec* rec0;       // [ntiles][NSLOTS] per tile: partials of its border components
     uint32_t* cnt0;      // [ntiles]
-    StatRec* rec1;       // [ngroups1][MERGE_HT] per 4 x 4 tiles: merged partials
-    uint32_t* cnt1;      // [ngroups1]
     int64_t nseg, nblk;
-    int32_t g1x, g1y;    // grid of first-level merge groups
+    int32_t g1x, g1y;    // grid of merge workgroups (4 x 4 tiles each)
     CompStats* comps;    // caller's output [capacity]
     int64_t capacity;
     int64_t* count;      // caller's output: number of components
@@ -134,11 +132,11 @@ struct StatsWs {
 inline int64_t stats_workspace_bytes(int64_t ntiles, int ntx, int nty)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    (void)ntx;
+    (void)nty;
     const int64_t nseg = ntiles * TILE_ROWS, nblk = (nseg + SCAN_BLK - 1) / SCAN_BLK;
-    const int64_t ng1 = (int64_t)((ntx + MERGE_FAN - 1) / MERGE_FAN) * ((nty + MERGE_FAN - 1) / MERGE_FAN);
     return up(nseg * 8) + up(nseg * 4) + 2 * up(nblk * 4) +
-           up(ntiles * NSLOTS * (int64_t)sizeof(StatRec)) + up(ntiles * 4) +
-           up(ng1 * MERGE_HT * (int64_t)sizeof(StatRec)) + up(ng1 * 4);
+           up(ntiles * NSLOTS * (int64_t)sizeof(StatRec)) + up(ntiles * 4);
 }
 
 inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
@@ -150,7 +148,6 @@ inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
     s.nblk = (s.nseg + SCAN_BLK - 1) / SCAN_BLK;
     s.g1x = (ntx + MERGE_FAN - 1) / MERGE_FAN;
     s.g1y = (nty + MERGE_FAN - 1) / MERGE_FAN;
-    const int64_t ng1 = (int64_t)s.g1x * s.g1y;
     s.rootbits = reinterpret_cast<uint64_t*>(p);
     p += up(s.nseg * 8);
     s.seg = reinterpret_cast<uint32_t*>(p);
@@ -162,10 +159,6 @@ inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
     s.rec0 = reinterpret_cast<StatRec*>(p);
     p += up(ntiles * NSLOTS * (int64_t)sizeof(StatRec));
     s.cnt0 = reinterpret_cast<uint32_t*>(p);
-    p += up(ntiles * 4);
-    s.rec1 = reinterpret_cast<StatRec*>(p);
-    p += up(ng1 * MERGE_HT * (int64_t)sizeof(StatRec));
-    s.cnt1 = reinterpret_cast<uint32_t*>(p);
     return s;
 }
 

@@ -28,7 +28,7 @@
 //            table (no union-find work is repeated).
 // Batches of images share one launch of each (k_index maps tiles, groups and
 // seam workgroups to their image).  Optional extras: per-component statistics
-// (k_scan1/2, k_stats_init, k_stats, k_stats_merge) and the paper's ablation
+// (k_scan1/2, k_stats, k_stats_merge) and the paper's ablation
 // variants of the local step (k_local_ablate).
 //
 // Labels are canonical: 1 + the smallest raster position of the component.
@@ -1235,24 +1235,6 @@ __global__ __launch_bounds__(SCAN_T) void k_scan2(StatsWs st)
     if (threadIdx.x == 0) st_global(st.count, (int64_t)carry);
 }
 
-// Neutral values for the accumulating fields of every numbered component
-// that fits the caller's array.
-__global__ __launch_bounds__(256) void k_stats_init(StatsWs st)
-{
-    const int64_t cnt = ld_global(st.count);
-    const int64_t n = cnt < st.capacity ? cnt : st.capacity;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        CompStats c;
-        c.label = 0;
-        c.area = 0;
-        c.x_min = c.y_min = INT32_MAX;
-        c.x_max = c.y_max = -1;
-        c.sum_x = c.sum_y = 0;
-        st_global(st.comps + i, c);
-    }
-}
-
 // Sum of the positions of the set bits of m.
 __device__ __forceinline__ uint32_t bit_position_sum(uint64_t m)
 {
@@ -1400,11 +1382,18 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
             sh.lab[rep] = L;
             if (!is_root) continue;  // only the label remains to write
         }
+        // the component's entry starts from its label and top row; the
+        // merge adds every tile's part to it
         const int64_t num = component_number(a, st, L);
         if (num >= st.capacity) continue;
-        CompStats* c = st.comps + num;
-        st_global(&c->label, L);
-        st_global(&c->y_min, (int32_t)(kpos / a.W));
+        CompStats c;
+        c.label = L;
+        c.area = 0;
+        c.x_min = INT32_MAX;
+        c.y_min = (int32_t)(kpos / a.W);
+        c.x_max = c.y_max = -1;
+        c.sum_x = c.sum_y = 0;
+        st_global(st.comps + num, c);
     }
     __syncthreads();
     // interior components: the whole entry from the run holding the smallest pixel
@@ -1457,35 +1446,30 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
     if (tid == 0) st.cnt0[T] = sh.nrec;
 }
 
-// One merge level: workgroup (I, J) combines the records of parts
-// (4I .. 4I+3, 4J .. 4J+3) of the level below (each `part_px` pixels square)
-// in an LDS hash table keyed by component number.  A combined record whose
-// box stays off the inner edges of the workgroup's region describes a whole
-// component (it cannot reach outside without crossing them) and goes to the
-// component's entry; the others are written out for the next level (FINAL =
-// false) or also go to the entries (FINAL).  Records that find the table
-// full go straight to the entries (atomics commute).
+// Merge of the tiles' partial records: workgroup (I, J) combines the
+// records of tiles (4I .. 4I+3, 4J .. 4J+3) in an LDS hash table keyed by
+// component number, then adds each combined record to the component's entry
+// with atomics (the entry was started by the tile holding the component's
+// smallest pixel).  A component that crosses regions meets its other parts
+// in those atomics; inside a region, most components' parts meet in LDS and
+// cost one set of atomics.  Records that find the table full go straight to
+// the entries (the atomics commute).
 constexpr int MERGE_T = 1024;
-template <bool FINAL>
 __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatRec* in,
                                                           const uint32_t* in_cnt, int in_cap,
-                                                          int inx, int iny, int part_px, int W,
-                                                          int H, StatRec* out, uint32_t* out_cnt,
-                                                          int outx)
+                                                          int inx, int iny, int outx)
 {
     __shared__ int32_t hkey[MERGE_HT], harea[MERGE_HT], hxmin[MERGE_HT], hxmax[MERGE_HT],
-        hymin[MERGE_HT], hymax[MERGE_HT];
+        hymax[MERGE_HT];
     __shared__ unsigned long long hsx[MERGE_HT], hsy[MERGE_HT];
-    __shared__ uint32_t nout;
     const int tid = threadIdx.x;
     for (int h = tid; h < MERGE_HT; h += MERGE_T) {
         hkey[h] = -1;
         harea[h] = 0;
-        hxmin[h] = hymin[h] = INT32_MAX;
+        hxmin[h] = INT32_MAX;
         hxmax[h] = hymax[h] = -1;
         hsx[h] = hsy[h] = 0ull;
     }
-    if (tid == 0) nout = 0u;
     __syncthreads();
     const int I = (int)(blockIdx.x % (unsigned)outx), J = (int)(blockIdx.x / (unsigned)outx);
     for (int part = 0; part < MERGE_FAN * MERGE_FAN; ++part) {
@@ -1504,7 +1488,6 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
                     atomicAdd(&harea[h], r.area);
                     atomicMin(&hxmin[h], r.x_min);
                     atomicMax(&hxmax[h], r.x_max);
-                    atomicMin(&hymin[h], r.y_min);
                     atomicMax(&hymax[h], r.y_max);
                     atomicAdd(&hsx[h], (unsigned long long)r.sum_x);
                     atomicAdd(&hsy[h], (unsigned long long)r.sum_y);
@@ -1517,33 +1500,9 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
         }
     }
     __syncthreads();
-    // the region's inner edges (image edges do not count)
-    const int span = part_px * MERGE_FAN;
-    const int x0 = I * span, y0 = J * span;
-    const int x1 = min(x0 + span, W) - 1, y1 = min(y0 + span, H) - 1;
     for (int h = tid; h < MERGE_HT; h += MERGE_T) {
         const int32_t num = hkey[h];
-        if (num < 0) continue;
-        const bool crosses = (hxmin[h] == x0 && x0 > 0) || (hxmax[h] == x1 && x1 < W - 1) ||
-                             (hymin[h] == y0 && y0 > 0) || (hymax[h] == y1 && y1 < H - 1);
-        if (FINAL || !crosses) {
-            add_stats(st.comps + num, harea[h], hxmin[h], hxmax[h], hymax[h], hsx[h], hsy[h]);
-        } else {
-            StatRec r;
-            r.num = num;
-            r.area = harea[h];
-            r.x_min = hxmin[h];
-            r.x_max = hxmax[h];
-            r.y_min = hymin[h];
-            r.y_max = hymax[h];
-            r.sum_x = (int64_t)hsx[h];
-            r.sum_y = (int64_t)hsy[h];
-            out[(int64_t)blockIdx.x * MERGE_HT + atomicAdd(&nout, 1u)] = r;
-        }
-    }
-    if (!FINAL) {
-        __syncthreads();
-        if (tid == 0) out_cnt[blockIdx.x] = nout;
+        if (num >= 0) add_stats(st.comps + num, harea[h], hxmin[h], hxmax[h], hymax[h], hsx[h], hsy[h]);
     }
 }
 
@@ -2053,19 +2012,10 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
     k_scan1<<<(unsigned)stats->nblk, SCAN_T, 0, st>>>(*stats);
     k_scan2<<<1, SCAN_T, 0, st>>>(*stats);
     if (stats->capacity > 0) {
-        const int64_t blocks = std::min<int64_t>((stats->capacity + 255) / 256, 4096);
-        k_stats_init<<<(unsigned)blocks, 256, 0, st>>>(*stats);
         k_stats<D><<<(unsigned)b.ntiles, ST, 0, st>>>(b, ws, *stats);
-        static_assert(TW == TILE_ROWS, "square tiles: merge regions are squares of tiles");
         const ImageArgs& a = b.one;
-        const int g2x = (stats->g1x + MERGE_FAN - 1) / MERGE_FAN;
-        const int g2y = (stats->g1y + MERGE_FAN - 1) / MERGE_FAN;
-        k_stats_merge<false><<<(unsigned)(stats->g1x * stats->g1y), MERGE_T, 0, st>>>(
-            *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, TW, a.W, a.H, stats->rec1,
-            stats->cnt1, stats->g1x);
-        k_stats_merge<true><<<(unsigned)(g2x * g2y), MERGE_T, 0, st>>>(
-            *stats, stats->rec1, stats->cnt1, MERGE_HT, stats->g1x, stats->g1y, TW * MERGE_FAN,
-            a.W, a.H, nullptr, nullptr, g2x);
+        k_stats_merge<<<(unsigned)(stats->g1x * stats->g1y), MERGE_T, 0, st>>>(
+            *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, stats->g1x);
     }
     timer_end(timer, KIND_STATS, st);
     return hipGetLastError();
