@@ -2,6 +2,7 @@
 // the per-(device, stream) workspace cache, and the optional event timer.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
@@ -110,7 +111,7 @@ struct KernelTimer {
 };
 
 static KernelTimer g_timer;
-static uint32_t g_timing_mask = 0;  // bit k: time kernel kind k
+static std::atomic<uint32_t> g_timing_mask{0};  // bit k: time kernel kind k
 
 void timer_begin(KernelTimer* t, int kind, hipStream_t st)
 {
@@ -263,16 +264,17 @@ static int bind_class(const std::vector<ImageArgs>& imgs, const ClassLayout& L, 
     return CCL_OK;
 }
 
-// Label images of one connectivity with one set of launches.  A single image
-// travels in the kernel arguments; several get a device table (copied into
-// the head of the workspace) that maps global tiles, merge groups and seam
-// workgroups back to their image.
 // Caller's outputs of the statistics path.
 struct StatsOut {
     ccl_component* comps;
     int64_t capacity;
     int64_t* count;
 };
+
+// Label images of one connectivity with one set of launches.  A single image
+// travels in the kernel arguments; several get a device table (copied into
+// the head of the workspace) that maps global tiles, merge groups and seam
+// workgroups back to their image.
 
 static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, bool local_only,
                      const char* who, const StatsOut* so = nullptr, int ablation = -1,
@@ -284,8 +286,7 @@ static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, boo
     if (rc != CCL_OK) return rc;
     const int64_t label_bytes = align256(L.bytes());
     void* base = nullptr;
-    rc = get_workspace(label_bytes + (so ? stats_workspace_bytes(L.ntiles, imgs[0].ntx, imgs[0].nty) : 0),
-                       st, &base);
+    rc = get_workspace(label_bytes + (so ? stats_workspace_bytes(L.ntiles) : 0), st, &base);
     if (rc != CCL_OK) return rc;
     BatchArgs b;
     Workspace ws;

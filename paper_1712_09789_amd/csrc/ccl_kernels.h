@@ -129,11 +129,9 @@ struct StatsWs {
     int64_t* count;      // caller's output: number of components
 };
 
-inline int64_t stats_workspace_bytes(int64_t ntiles, int ntx, int nty)
+inline int64_t stats_workspace_bytes(int64_t ntiles)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
-    (void)ntx;
-    (void)nty;
     const int64_t nseg = ntiles * TILE_ROWS, nblk = (nseg + SCAN_BLK - 1) / SCAN_BLK;
     return up(nseg * 8) + up(nseg * 4) + 2 * up(nblk * 4) +
            up(ntiles * NSLOTS * (int64_t)sizeof(StatRec)) + up(ntiles * 4);
