@@ -232,6 +232,30 @@ def test_repeated_labelling_4096(ccl):
     print("[parity] repeated 4096 labellings: 96 exact", flush=True)
 
 
+def test_repeated_merge_heavy_8192(ccl):
+    """Repeated labellings whose merge across groups does most of the work:
+    one component threaded through every merge group (spiral, serpentine),
+    where finds walk long chains while other unions rewrite them, and a
+    density near the percolation threshold.  Spiral and serpentine are single
+    components with (0, 0) in the foreground, so every foreground label is 1;
+    the Bernoulli image is compared with the oracle."""
+    out = torch.empty((8192, 8192), dtype=torch.int32, device="cuda")
+    for kind, kw in (("spiral", {}), ("serpentine", {"width": 1})):
+        img = cached(kind, 8192, 8192, 0, tuple(sorted(kw.items())))
+        dimg, fg = to_dev(img), torch.from_numpy(img != 0).cuda()
+        for rep in range(3):
+            ccl.label(dimg, 8, out=out)
+            torch.cuda.synchronize()
+            assert bool((out[fg] == 1).all()) and bool((out[~fg] == 0).all()), (kind, rep)
+    img = cached("bernoulli", 8192, 8192, 3, (("p", 0.6),))
+    dimg, want = to_dev(img), oracle_label(img, 4)
+    for rep in range(3):
+        ccl.label(dimg, 4, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), ("bernoulli0.6", rep)
+    print("[parity] repeated merge-heavy 8192 labellings exact", flush=True)
+
+
 @pytest.mark.parametrize("kind,kw", wl.ADVERSARIAL)
 def test_c3_8192_adversarial(ccl, kind, kw):
     img = wl.make(kind, 8192, 8192, **kw)
