@@ -721,6 +721,12 @@ def main():
         "copy_GBs": round(copy_gbs, 1),
         "path_copy_frac": round(PATH_BYTES_PER_PX * value / copy_gbs, 4),
         "kernel_avg_us": kavg,
+        # every kernel with algorithmic bytes, against HBM peak (durations from
+        # the region with events around every kernel)
+        "kernel_hbm": {KERNEL_NAMES[k]: {
+            "GBs": round(KERNEL_BYTES_PER_PX[k] * px / (kavg[k] * 1e-6) / 1e9, 1),
+            "frac": round(KERNEL_BYTES_PER_PX[k] * px / (kavg[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+            for k in KERNEL_BYTES_PER_PX if kavg.get(k)},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

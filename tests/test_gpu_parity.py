@@ -186,6 +186,20 @@ def test_tile_independent_of_history(ccl):
     assert np.array_equal(gpu_label(ccl, a, 8), first)
 
 
+def test_random_sweep(ccl):
+    """Seeded sweep over shapes (ragged in both axes, 1 to 700), densities and
+    contents, both connectivities: 80 images, each against the oracle."""
+    rng = np.random.default_rng(2024)
+    for trial in range(80):
+        H, W = (int(v) for v in rng.integers(1, 701, 2))
+        conn = int(rng.choice([4, 8]))
+        if trial % 4 == 3 and min(H, W) >= 8:
+            img = wl.blobs(H, W, float(rng.choice([2.0, 4.0])), seed=trial)
+        else:
+            img = wl.bernoulli(H, W, float(rng.uniform(0.05, 0.95)), seed=trial)
+        assert_parity(ccl, img, conn, f"sweep {trial}")
+
+
 # --- configs at full size ---------------------------------------------------
 
 @pytest.mark.parametrize("seed", range(5))
