@@ -154,8 +154,9 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
  *   connectivity  6 (face neighbours) or 26 (the 3 x 3 x 3 block).
  *   labels        device, int32, dense D * H * W; caller-owned, fully
  *                 overwritten.  Must not overlap vol.
- * Errors as ccl_label (CCL_ERR_TOO_LARGE when D * H * W > 2^31 - 1); an empty
- * volume is a no-op.
+ * Errors as ccl_label (CCL_ERR_TOO_LARGE when D * H * W > 2^31 - 1, or when
+ * the D slices together have more than (2^31 - 1) / 256 tiles, as very thin
+ * slices can); an empty volume is a no-op.
  */
 int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pitch_bytes,
                  int64_t slice_pitch_bytes, int32_t connectivity, int32_t* labels, void* stream);

@@ -395,6 +395,10 @@ int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pi
                                           (int64_t)(H - 1) * pitch_bytes + W);
     const uintptr_t l0 = (uintptr_t)labels, l1 = l0 + (uintptr_t)((int64_t)D * H * W * 4);
     if (v0 < l1 && l0 < v1) return fail(CCL_ERR_INVALID_ARG, "%s: vol and labels overlap", who);
+    const int64_t tiles = (int64_t)D * ((W + TW - 1) / TW) * ((H + TILE_ROWS - 1) / TILE_ROWS);
+    if (tiles * NSLOTS > (int64_t)INT32_MAX)
+        return fail(CCL_ERR_TOO_LARGE, "%s: %lld tiles over all slices exceed the node id range",
+                    who, (long long)tiles);
     const int conn2 = connectivity == 6 ? 4 : 8;  // the in-slice part of the neighbourhood
     std::vector<ImageArgs> slices;
     slices.reserve(D);
