@@ -1247,14 +1247,16 @@ template <int D>
 struct StatsShared : Lines<D> {
     uint16_t RL[Geo<D>::MAXR];
     alignas(16) uint16_t ent[RUNTAB_PER_TILE];  // the tile's run table
-    // border components of the tile, accumulated by representative slot
-    // (tile-local coordinates)
-    int32_t area[NSLOTS], xmin[NSLOTS], xmax[NSLOTS], ymin[NSLOTS], ymax[NSLOTS];
-    uint32_t sx[NSLOTS], sy[NSLOTS];
+    // Per component part, in tile-local coordinates, three words that take
+    // one atomic each per run: the packed sums (area | sum x << 13 | sum y
+    // << 31; a tile's totals fit 13, 18 and 18 bits, so no field carries into
+    // the next), and the masks of the columns and of the rows it touches (the
+    // box is their lowest and highest set bits).
+    // border components of the tile, by representative slot
+    uint64_t sums[NSLOTS], cols[NSLOTS], rows[NSLOTS];
     int32_t lab[NSLOTS];
-    // interior components, accumulated at the run holding their smallest pixel
-    int32_t iarea[Geo<D>::MAXR], ixmin[Geo<D>::MAXR], ixmax[Geo<D>::MAXR], iymax[Geo<D>::MAXR];
-    uint32_t isx[Geo<D>::MAXR], isy[Geo<D>::MAXR];
+    // interior components, at the run holding their smallest pixel
+    uint64_t isums[Geo<D>::MAXR], icols[Geo<D>::MAXR], irows[Geo<D>::MAXR];
     uint8_t iroot[Geo<D>::MAXR];
     uint32_t nrec;
 };
@@ -1307,10 +1309,7 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
 
     if (tid < TILE_ROWS) sh.M[tid] = ws.bits[T * TILE_ROWS + tid];
     if (tid < NSLOTS) {
-        sh.area[tid] = 0;
-        sh.xmin[tid] = sh.ymin[tid] = INT32_MAX;
-        sh.xmax[tid] = sh.ymax[tid] = -1;
-        sh.sx[tid] = sh.sy[tid] = 0u;
+        sh.sums[tid] = sh.cols[tid] = sh.rows[tid] = 0ull;
     }
     if (tid == 0) sh.nrec = 0u;
     __syncthreads();
@@ -1321,10 +1320,7 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         reinterpret_cast<uint4*>(sh.ent)[tid] =
             reinterpret_cast<const uint4*>(ws.runtab + T * RUNTAB_PER_TILE)[tid];
     for (uint32_t id = tid; id < R; id += ST) {
-        sh.iarea[id] = 0;
-        sh.ixmin[id] = INT32_MAX;
-        sh.ixmax[id] = sh.iymax[id] = -1;
-        sh.isx[id] = sh.isy[id] = 0u;
+        sh.isums[id] = sh.icols[id] = sh.irows[id] = 0ull;
         sh.iroot[id] = 0;
     }
     __syncthreads();
@@ -1332,10 +1328,11 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         const uint32_t rec = sh.RL[id];
         const int s0 = rec & 63, l = rec >> 6;
         const int e = s0 + ctz64_or64(~(sh.LM[l] >> s0)) - 1;
-        uint32_t area, ymin, ymax, key, sx, sy;
+        uint32_t area, key, sx, sy;
+        uint64_t rowm;  // rows of the tile the run's pixels lie in
         if (!D) {
             area = (uint32_t)(e - s0 + 1);
-            ymin = ymax = (uint32_t)l;
+            rowm = 1ull << l;
             sx = (uint32_t)(s0 + e) * area / 2u;
             sy = (uint32_t)l * area;
             key = (uint32_t)(l * TW + s0);
@@ -1344,12 +1341,14 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
             const uint64_t top = sh.M[2 * l] & span, bot = sh.M[2 * l + 1] & span;
             const uint32_t at = popc64(top), ab = popc64(bot);
             area = at + ab;
-            ymin = top ? 2u * l : 2u * l + 1u;
-            ymax = bot ? 2u * l + 1u : 2u * l;
+            rowm = (top ? 1ull << (2 * l) : 0ull) | (bot ? 1ull << (2 * l + 1) : 0ull);
             sx = bit_position_sum(top) + bit_position_sum(bot);
             sy = (uint32_t)(2 * l) * at + (uint32_t)(2 * l + 1) * ab;
             key = top ? (uint32_t)(2 * l * TW + ctz64(top)) : (uint32_t)((2 * l + 1) * TW + s0);
         }
+        // its first and last columns are foreground (in one of its rows)
+        const uint64_t colm = span_mask(s0, e);
+        const uint64_t packed = (uint64_t)area | ((uint64_t)sx << 13) | ((uint64_t)sy << 31);
         const int64_t kpos = (int64_t)(gy0 + (int)(key / TW)) * a.W + gx0 + (int)(key % TW);
         const int32_t L = ld_global(a.labels + kpos);
         if (L <= 0 || (int64_t)L > kpos + 1) continue;  // not a label of this pixel
@@ -1361,24 +1360,17 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
             const int ky = (int)(en / TW), kx = (int)(en % TW);
             const int rl = D ? ky >> 1 : ky;
             const uint32_t rr = sh.base[rl] + popc64(sh.LS[rl] & upto(kx)) - 1u;
-            atomicAdd(&sh.iarea[rr], (int)area);
-            atomicMin(&sh.ixmin[rr], s0);
-            atomicMax(&sh.ixmax[rr], e);
-            atomicMax(&sh.iymax[rr], (int)ymax);
-            atomicAdd(&sh.isx[rr], sx);
-            atomicAdd(&sh.isy[rr], sy);
+            atomicAdd(&sh.isums[rr], packed);
+            atomicOr(&sh.icols[rr], colm);
+            atomicOr(&sh.irows[rr], rowm);
             if (is_root) sh.iroot[id] = 1;
             continue;
         }
         {
             const int rep = en & 0x7fff;
-            atomicAdd(&sh.area[rep], (int)area);
-            atomicMin(&sh.xmin[rep], s0);
-            atomicMax(&sh.xmax[rep], e);
-            atomicMin(&sh.ymin[rep], (int)ymin);
-            atomicMax(&sh.ymax[rep], (int)ymax);
-            atomicAdd(&sh.sx[rep], sx);
-            atomicAdd(&sh.sy[rep], sy);
+            atomicAdd(&sh.sums[rep], packed);
+            atomicOr(&sh.cols[rep], colm);
+            atomicOr(&sh.rows[rep], rowm);
             sh.lab[rep] = L;
             if (!is_root) continue;  // only the label remains to write
         }
@@ -1413,32 +1405,35 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         const int32_t L = (int32_t)(kpos + 1);
         const int64_t num = component_number(a, st, L);
         if (num >= st.capacity) continue;
-        const int area = sh.iarea[id];
+        const uint64_t v = sh.isums[id], cm = sh.icols[id], rm = sh.irows[id];
+        const int area = (int)(v & 0x1fffu);
         CompStats c;
         c.label = L;
         c.area = area;
-        c.x_min = gx0 + sh.ixmin[id];
+        c.x_min = gx0 + ctz64(cm);
         c.y_min = gy0 + ky;
-        c.x_max = gx0 + sh.ixmax[id];
-        c.y_max = gy0 + sh.iymax[id];
-        c.sum_x = (int64_t)(sh.isx[id] + (uint64_t)area * gx0);
-        c.sum_y = (int64_t)(sh.isy[id] + (uint64_t)area * gy0);
+        c.x_max = gx0 + msb64(cm);
+        c.y_max = gy0 + msb64(rm);
+        c.sum_x = (int64_t)(((v >> 13) & 0x3ffffu) + (uint64_t)area * gx0);
+        c.sum_y = (int64_t)(((v >> 31) & 0x3ffffu) + (uint64_t)area * gy0);
         st_global(st.comps + num, c);
     }
     // one partial record per border component of the tile
-    const int area = tid < NSLOTS ? sh.area[tid] : 0;
+    const uint64_t v = tid < NSLOTS ? sh.sums[tid] : 0ull;
+    const int area = (int)(v & 0x1fffu);
     if (area > 0) {
         const int64_t num = component_number(a, st, sh.lab[tid]);
         if (num < st.capacity) {
             StatRec r;
             r.num = (int32_t)num;
             r.area = area;
-            r.x_min = gx0 + sh.xmin[tid];
-            r.x_max = gx0 + sh.xmax[tid];
-            r.y_min = gy0 + sh.ymin[tid];
-            r.y_max = gy0 + sh.ymax[tid];
-            r.sum_x = (int64_t)(sh.sx[tid] + (uint64_t)area * gx0);
-            r.sum_y = (int64_t)(sh.sy[tid] + (uint64_t)area * gy0);
+            const uint64_t cm = sh.cols[tid], rm = sh.rows[tid];
+            r.x_min = gx0 + ctz64(cm);
+            r.x_max = gx0 + msb64(cm);
+            r.y_min = gy0 + ctz64(rm);
+            r.y_max = gy0 + msb64(rm);
+            r.sum_x = (int64_t)(((v >> 13) & 0x3ffffu) + (uint64_t)area * gx0);
+            r.sum_y = (int64_t)(((v >> 31) & 0x3ffffu) + (uint64_t)area * gy0);
             st.rec0[T * NSLOTS + atomicAdd(&sh.nrec, 1u)] = r;
         }
     }
