@@ -1291,9 +1291,10 @@ __device__ __forceinline__ int64_t component_number(const ImageArgs& a, const St
 // this tile) are summed in LDS at the run holding the component's smallest
 // pixel, which then writes the whole entry; runs of border components are
 // summed per component in LDS and leave the tile as one partial record each,
-// which two merge levels combine before they reach the entries, so that a
-// component spanning the image is not updated once per tile.  The run
-// holding a border component's smallest pixel writes its label and top row.
+// which k_stats_merge combines over 4 x 4 tiles before they reach the
+// entries, so that a component spanning the image is not updated once per
+// tile.  The run holding a border component's smallest pixel writes the
+// entry's starting values (label, top row, empty sums and box).
 constexpr int ST = 1024;  // k_stats threads per tile: latency of the per-run loads is hidden
                           // inside the workgroup (its LDS allows two per compute unit)
 template <int D>
