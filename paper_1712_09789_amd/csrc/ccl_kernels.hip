@@ -1732,26 +1732,36 @@ __device__ __forceinline__ uint32_t vl_hop(const int32_t* p, int step)
            1u;
 }
 
-// Entries always name smaller positions, so a chase ends at a root; the
-// bound check only keeps a corrupted entry from reading outside the map.
-__device__ uint32_t v_find(int32_t* lab, uint32_t r, uint32_t n)
+// Root of r, given its parent p and grandparent pp (p not a root, pp != p):
+// halves the path on the way.  Entries always name smaller positions, so a
+// chase ends at a root; the bound check only keeps a corrupted entry from
+// reading outside the map.
+__device__ uint32_t v_find_on(int32_t* lab, uint32_t r, uint32_t p, uint32_t pp, uint32_t n)
 {
-    for (int step = 0;; step += 2) {
-        const uint32_t p = vl_hop(lab + r, step);
-        if (p == r || p >= n) return r;
-        const uint32_t pp = vl_hop(lab + p, step + 1);
-        if (pp == p || pp >= n) return p;
+    for (int step = 2;; step += 2) {
         __hip_atomic_fetch_min(lab + r, (int32_t)(pp + 1u), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         r = pp;
+        p = vl_hop(lab + r, step);
+        if (p == r || p >= n) return r;
+        pp = vl_hop(lab + p, step + 1);
+        if (pp == p || pp >= n) return p;
     }
 }
 
 __device__ void v_union(int32_t* lab, uint32_t a, uint32_t b, uint32_t n)
 {
     while (true) {
-        a = v_find(lab, a, n);
-        b = v_find(lab, b, n);
+        // the first two hops of both finds, each hop's two loads issued
+        // together (most finds end within them)
+        uint32_t pa = vl_hop(lab + a, 0), pb = vl_hop(lab + b, 0);
+        if (pa >= n) pa = a;
+        if (pb >= n) pb = b;
+        uint32_t qa = pa, qb = pb;
+        if (pa != a) qa = vl_hop(lab + pa, 1);
+        if (pb != b) qb = vl_hop(lab + pb, 1);
+        if (pa != a) a = (qa == pa || qa >= n) ? pa : v_find_on(lab, a, pa, qa, n);
+        if (pb != b) b = (qb == pb || qb >= n) ? pb : v_find_on(lab, b, pb, qb, n);
         if (a == b) return;
         if (a < b) { const uint32_t t = a; a = b; b = t; }
         const int32_t old = __hip_atomic_fetch_min(lab + a, (int32_t)(b + 1u), __ATOMIC_RELAXED,
