@@ -171,7 +171,7 @@ static ImageArgs make_args(const uint8_t* img, int32_t H, int32_t W, int64_t pit
     a.ntx = (W + TW - 1) / TW;
     a.nty = (H + TILE_ROWS - 1) / TILE_ROWS;
     (void)conn;  // the launch carries the connectivity (one per batch class)
-    a.vec_in = ((uintptr_t)img % 16 == 0) && (pitch % 16 == 0);
+    a.unused = 0;
     a.vec_out = ((uintptr_t)labels % 16 == 0) && (W % 4 == 0);
     a.wmagic = W == 1 ? 0xffffffffu : (uint32_t)((1ull << 32) / (uint64_t)W);
     a.lbase = 0;

@@ -25,7 +25,7 @@ struct ImageArgs {
     int32_t ntx, nty;  // tile grid
     uint32_t wmagic;   // floor(2^32 / W) (0xffffffff for W = 1), for division by W
     int32_t lbase;     // added to every label written (a slice's first voxel position)
-    int32_t vec_in;    // img and pitch are 16-byte aligned
+    int32_t unused;    // keeps the layout at 64 bytes
     int32_t vec_out;   // labels rows are 16-byte aligned (W % 4 == 0)
     int64_t tbase;     // global index of the image's first tile in the workspace
 };

@@ -454,33 +454,50 @@ __global__ __launch_bounds__(256) void k_index(BatchArgs b)
 // k_local
 // ---------------------------------------------------------------------------
 
-// Initialisation (Section 3.1.1): sixteen bytes of a tile, four threads per
-// row.  Bytes past the image edge read as background.  The raw bytes are
-// returned so that the load of the next tile can be in flight while the
-// current one is labelled.
-__device__ __forceinline__ uint4 fetch_chunk(const ImageArgs& a, int t, int c)
+// Initialisation (Section 3.1.1): sixteen pixels of a tile row, four threads
+// per row.  The bytes come from the aligned 16-byte blocks that hold them:
+// one block when the row segment is aligned (rows of an image with an
+// aligned base and pitch), else two, and the foreground mask is shifted into
+// place.  A block is loaded only when it holds a byte of the segment, so it
+// lies in the same memory page as image bytes (blocks never cross a page);
+// its other bytes are masked off, as are pixels past the image edge.  The
+// raw blocks are returned so that the loads of the next tile can be in
+// flight while the current one is labelled.
+struct Chunk {
+    uint4 lo, hi;   // the aligned blocks
+    uint32_t off;   // byte of the segment's first pixel in lo
+    uint32_t n;     // pixels of the segment inside the image (0 .. 16)
+};
+__device__ __forceinline__ Chunk fetch_chunk(const ImageArgs& a, int t, int c)
 {
     const int gx = (t % a.ntx) * TW + 16 * (c & 3);
     const int gy = (t / a.ntx) * TILE_ROWS + (c >> 2);
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    Chunk k;
+    k.lo = k.hi = make_uint4(0u, 0u, 0u, 0u);
+    k.off = k.n = 0u;
     if (gy < a.H && gx < a.W) {
         const uint8_t* src = a.img + (int64_t)gy * a.pitch + gx;
-        if (a.vec_in && gx + 16 <= a.W) {
-            v = ld_global16(src);
-        } else {
-            const int n = a.W - gx < 16 ? a.W - gx : 16;
-            uint32_t w[4] = {0u, 0u, 0u, 0u};
-            for (int i = 0; i < n; ++i) w[i >> 2] |= (uint32_t)ld_global(src + i) << (8 * (i & 3));
-            v = make_uint4(w[0], w[1], w[2], w[3]);
-        }
+        k.n = (uint32_t)(a.W - gx < 16 ? a.W - gx : 16);
+        k.off = (uint32_t)((uintptr_t)src & 15u);
+        const uint8_t* blk = src - k.off;
+        k.lo = ld_global16(blk);
+        if (k.off + k.n > 16u) k.hi = ld_global16(blk + 16);
     }
-    return v;
+    return k;
 }
 
 // Foreground bits of sixteen bytes (bit i = byte i != 0).
-__device__ __forceinline__ uint32_t chunk_mask(uint4 v)
+__device__ __forceinline__ uint32_t nz16(uint4 v)
 {
     return nz_nibble(v.x) | (nz_nibble(v.y) << 4) | (nz_nibble(v.z) << 8) | (nz_nibble(v.w) << 12);
+}
+
+// Foreground bits of the chunk's pixels (bit i = pixel i).
+__device__ __forceinline__ uint32_t chunk_mask(const Chunk& k)
+{
+    uint32_t m = nz16(k.lo);
+    if (k.off + k.n > 16u) m |= nz16(k.hi) << 16;
+    return (m >> k.off) & ((1u << k.n) - 1u);
 }
 
 // The local step on tile t; sh.u.h holds its foreground bits on entry.
@@ -686,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_local(BatchArgs b, Workspace ws)
     if (T >= b.ntiles) return;
     ImageArgs a = batch_image(b, tile_image(b, T));
     int t = (int)(T - a.tbase);
-    uint4 raw = fetch_chunk(a, t, tid);
+    Chunk raw = fetch_chunk(a, t, tid);
     for (; T < b.ntiles; T += gridDim.x) {
         sh.u.h[tid] = (uint16_t)chunk_mask(raw);
         const int64_t TN = T + gridDim.x;
