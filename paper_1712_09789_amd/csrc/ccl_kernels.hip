@@ -1137,28 +1137,44 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
 
     // write the labels: 16 threads per tile row, 4 pixels per thread
     const int xmax = a.W - gx0;  // pixels of this tile inside the image
-    for (int c = tid; c < TILE_ROWS * 16; c += NT) {
-        const int r = c >> 4, x0 = (c & 15) * 4;
-        const int gy = gy0 + r;
-        if (gy >= a.H || x0 >= xmax) continue;
-        const int l = D ? r >> 1 : r;
-        const uint64_t ls = sh.LS[l];
-        const uint32_t m4 = (uint32_t)(sh.M[r] >> x0) & 15u;
-        const uint32_t s4 = (uint32_t)(ls >> x0) & 15u;
-        uint32_t cnt = sh.base[l] + popc64(ls & ~(~0ull << x0));  // runs starting left of x0
-        int32_t o[4];
+    if (a.vec_out && xmax >= TW) {
+        // whole aligned rows: four consecutive pixels per thread, one
+        // 16-byte store
+        for (int c = tid; c < TILE_ROWS * 16; c += NT) {
+            const int r = c >> 4, x0 = (c & 15) * 4;
+            const int gy = gy0 + r;
+            if (gy >= a.H) continue;
+            const int l = D ? r >> 1 : r;
+            const uint64_t ls = sh.LS[l];
+            const uint32_t m4 = (uint32_t)(sh.M[r] >> x0) & 15u;
+            const uint32_t s4 = (uint32_t)(ls >> x0) & 15u;
+            uint32_t cnt = sh.base[l] + popc64(ls & ~(~0ull << x0));  // runs starting left of x0
+            int32_t o[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            cnt += (s4 >> k) & 1u;
-            // a foreground pixel has its run start at or left of it, so cnt >= 1
-            o[k] = ((m4 >> k) & 1u) ? sh.lab[cnt ? cnt - 1 : 0] : 0;
+            for (int k = 0; k < 4; ++k) {
+                cnt += (s4 >> k) & 1u;
+                // a foreground pixel has its run start at or left of it, so cnt >= 1
+                o[k] = ((m4 >> k) & 1u) ? sh.lab[cnt ? cnt - 1 : 0] : 0;
+            }
+            st_global16(a.labels + (int64_t)gy * a.W + gx0 + x0, o[0], o[1], o[2], o[3]);
         }
-        int32_t* dst = a.labels + (int64_t)gy * a.W + gx0 + x0;
-        if (a.vec_out && x0 + 4 <= xmax) {
-            st_global16(dst, o[0], o[1], o[2], o[3]);
-        } else {
-            const int n = xmax - x0 < 4 ? xmax - x0 : 4;
-            for (int k = 0; k < n; ++k) st_global(dst + k, o[k]);
+    } else {
+        // rows not 16-byte aligned, or cut by the image edge: pixels
+        // x, x + 16, x + 32, x + 48 per thread, so that each store
+        // instruction writes sixteen consecutive labels of a row
+        for (int c = tid; c < TILE_ROWS * 16; c += NT) {
+            const int r = c >> 4, x = c & 15;
+            const int gy = gy0 + r;
+            if (gy >= a.H) continue;
+            const int l = D ? r >> 1 : r;
+            const uint64_t m = sh.M[r];
+            int32_t* row = a.labels + (int64_t)gy * a.W + gx0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int xk = x + 16 * k;
+                if (xk < xmax)
+                    st_global(row + xk, ((m >> xk) & 1ull) ? sh.lab[run_id<D>(sh, l, xk)] : 0);
+            }
         }
     }
 }
