@@ -1477,28 +1477,33 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
 
 // Merge of the tiles' partial records: workgroup (I, J) combines the
 // records of tiles (4I .. 4I+3, 4J .. 4J+3) in an LDS hash table keyed by
-// component number, then adds each combined record to the component's entry
-// with atomics (the entry was started by the tile holding the component's
-// smallest pixel).  A component that crosses regions meets its other parts
-// in those atomics; inside a region, most components' parts meet in LDS and
-// cost one set of atomics.  Records that find the table full go straight to
-// the entries (the atomics commute).
+// component number.  A combined record whose box stays off the region's
+// inner edges (image edges do not count) is the whole component: it cannot
+// reach outside without crossing them, so its fields are stored into the
+// component's entry (started by the tile holding its smallest pixel, which
+// wrote the label and top row).  The others are added to the entry with
+// atomics, where a component's parts from several regions meet.  Records
+// that find the table full go straight to the entries with atomics; then
+// the workgroup stores nothing plainly, since a store could hide them.
 constexpr int MERGE_T = 1024;
 __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatRec* in,
                                                           const uint32_t* in_cnt, int in_cap,
-                                                          int inx, int iny, int outx)
+                                                          int inx, int iny, int outx, int W,
+                                                          int H)
 {
     __shared__ int32_t hkey[MERGE_HT], harea[MERGE_HT], hxmin[MERGE_HT], hxmax[MERGE_HT],
-        hymax[MERGE_HT];
+        hymin[MERGE_HT], hymax[MERGE_HT];
     __shared__ unsigned long long hsx[MERGE_HT], hsy[MERGE_HT];
+    __shared__ int overflow;
     const int tid = threadIdx.x;
     for (int h = tid; h < MERGE_HT; h += MERGE_T) {
         hkey[h] = -1;
         harea[h] = 0;
-        hxmin[h] = INT32_MAX;
+        hxmin[h] = hymin[h] = INT32_MAX;
         hxmax[h] = hymax[h] = -1;
         hsx[h] = hsy[h] = 0ull;
     }
+    if (tid == 0) overflow = 0;
     __syncthreads();
     const int I = (int)(blockIdx.x % (unsigned)outx), J = (int)(blockIdx.x / (unsigned)outx);
     for (int part = 0; part < MERGE_FAN * MERGE_FAN; ++part) {
@@ -1517,21 +1522,42 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
                     atomicAdd(&harea[h], r.area);
                     atomicMin(&hxmin[h], r.x_min);
                     atomicMax(&hxmax[h], r.x_max);
+                    atomicMin(&hymin[h], r.y_min);
                     atomicMax(&hymax[h], r.y_max);
                     atomicAdd(&hsx[h], (unsigned long long)r.sum_x);
                     atomicAdd(&hsy[h], (unsigned long long)r.sum_y);
                     placed = true;
                 }
             }
-            if (!placed)
+            if (!placed) {
+                overflow = 1;
                 add_stats(st.comps + r.num, r.area, r.x_min, r.x_max, r.y_max,
                           (uint64_t)r.sum_x, (uint64_t)r.sum_y);
+            }
         }
     }
     __syncthreads();
+    // the region's inner edges
+    const int span = TW * MERGE_FAN;
+    const int x0 = I * span, y0 = J * span;
+    const int x1 = min(x0 + span, W) - 1, y1 = min(y0 + span, H) - 1;
+    const bool plain_ok = overflow == 0;
     for (int h = tid; h < MERGE_HT; h += MERGE_T) {
         const int32_t num = hkey[h];
-        if (num >= 0) add_stats(st.comps + num, harea[h], hxmin[h], hxmax[h], hymax[h], hsx[h], hsy[h]);
+        if (num < 0) continue;
+        const bool crosses = (hxmin[h] == x0 && x0 > 0) || (hxmax[h] == x1 && x1 < W - 1) ||
+                             (hymin[h] == y0 && y0 > 0) || (hymax[h] == y1 && y1 < H - 1);
+        CompStats* c = st.comps + num;
+        if (crosses || !plain_ok) {
+            add_stats(c, harea[h], hxmin[h], hxmax[h], hymax[h], hsx[h], hsy[h]);
+        } else {
+            st_global(&c->area, harea[h]);
+            st_global(&c->x_min, hxmin[h]);
+            st_global(&c->x_max, hxmax[h]);
+            st_global(&c->y_max, hymax[h]);
+            st_global(&c->sum_x, (int64_t)hsx[h]);
+            st_global(&c->sum_y, (int64_t)hsy[h]);
+        }
     }
 }
 
@@ -2053,8 +2079,9 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
     if (stats->capacity > 0) {
         k_stats<D><<<(unsigned)b.ntiles, ST, 0, st>>>(b, ws, *stats);
         const ImageArgs& a = b.one;
+        static_assert(TW == TILE_ROWS, "square tiles: merge regions are squares of tiles");
         k_stats_merge<<<(unsigned)(stats->g1x * stats->g1y), MERGE_T, 0, st>>>(
-            *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, stats->g1x);
+            *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, stats->g1x, a.W, a.H);
     }
     timer_end(timer, KIND_STATS, st);
     return hipGetLastError();
