@@ -1836,9 +1836,10 @@ __device__ void v_union(int32_t* lab, uint32_t a, uint32_t b, uint32_t n)
 // rim of one row and one column, which 26-connectivity reaches.  The work is
 // done per run: each maximal stretch of foreground in a block row of slice z
 // lies in one slice component, so one label names it, and it is united with
-// every run of slice z-1 it touches (again one label each): the run directly
-// below for 6-connectivity; for 26 the runs in the three rows around it, one
-// column further on each side, the rim included.  A run that crosses the
+// every run of slice z-1 it touches (again one label each): for
+// 6-connectivity the runs of the same row that share a column with it; for
+// 26 the runs in the three rows around it, one column further on each side,
+// the rim included.  A run that crosses the
 // block's edge is cut there; the two parts together touch the same runs.  A
 // thread drops a pair equal to the one it united last, and the workgroup
 // drops pairs another of its threads already holds (LDS hash, as in k_seam).
@@ -1846,10 +1847,6 @@ __device__ void v_union(int32_t* lab, uint32_t a, uint32_t b, uint32_t n)
 // ancestor of a component serves.
 constexpr int ZB_W = 64, ZB_H = 16;  // block of a slice pair
 constexpr int ZM_HASH = 1024;
-__device__ __forceinline__ uint64_t bit_range(int lo, int hi)  // bits lo .. hi, 0 <= lo <= hi <= 63
-{
-    return (~0ull >> (63 - hi)) & (~0ull << lo);
-}
 template <int C>
 __global__ __launch_bounds__(256) void k_zmerge(VolArgs v, int nbx, int nby)
 {
@@ -1920,7 +1917,7 @@ __global__ __launch_bounds__(256) void k_zmerge(VolArgs v, int nbx, int nby)
         const uint32_t a = (uint32_t)clab[ty][c] - 1u;
         const int lo = C == 26 ? c - 1 : c, hi = C == 26 ? e + 1 : e;  // columns touched
         for (int pr = C == 26 ? ty : ty + 1; pr <= (C == 26 ? ty + 2 : ty + 1); ++pr) {
-            const uint64_t q = pm[pr] & bit_range(lo < 0 ? 0 : lo, hi > 63 ? 63 : hi);
+            const uint64_t q = pm[pr] & span_mask(lo < 0 ? 0 : lo, hi > 63 ? 63 : hi);
             for (uint64_t s2 = q & ~(q << 1); s2; s2 &= s2 - 1)
                 unite(a, plab[pr][__builtin_ctzll(s2) + 1]);
             // rim voxels, unless the run through column 0 / 63 already reached them
