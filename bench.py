@@ -578,8 +578,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(images are independent; see the sharding design). Run with --gpus 1.",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(images are independent, so batches shard by whole images). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
