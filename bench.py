@@ -9,7 +9,7 @@ Infinity Cache.  A step labels one image (all four kernels).  Inputs are
 resident in HBM before timing starts; host<->device copies are not timed.
 Besides the aggregate rate over the timed steps, the per-step median, minimum
 and 99th percentile (events between steps) and the rate of the library's copy
-kernel (the achievable HBM bandwidth on the box) are reported.
+kernel (the achievable HBM bandwidth of the device) are reported.
 
 The result is only reported as exact if every image's labels equal the CPU
 checker's (element-by-element, after a warm-up run), which is also timed on
