@@ -146,6 +146,37 @@ def summarize_trace(db, out, cmd):
         fh.write("\n".join(lines) + "\n")
 
 
+def summarize_counters(db, out, cmd, px=4096 * 4096):
+    """Counter database (one rocprofv3 --pmc run) -> markdown table of each
+    counter's mean per dispatch, per kernel, and per pixel of a launch."""
+    import collections
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, counter_name, dispatch_id, sum(value) from "
+                       "counters_collection group by dispatch_id, counter_name").fetchall()
+    agg = collections.defaultdict(list)
+    for name, counter, _, v in rows:
+        agg[(_short_kernel(name), counter)].append(v)
+    counters = sorted({c for _, c in agg})
+    kernels = sorted({k for k, _ in agg if k.startswith("k_") and k != "k_copy"})
+    lines = ["# Counters per launch: " + os.path.basename(out).rsplit(".", 1)[0], "",
+             "Produced by:", "", "```", cmd, "```", "",
+             f"kernel_source_hash: {kernel_source_hash()}", "",
+             "Mean per launch (per pixel of a 4096x4096 launch in brackets).", "",
+             "| kernel | launches | " + " | ".join(counters) + " |",
+             "|---|---|" + "---|" * len(counters)]
+    for k in kernels:
+        n = max(len(agg[(k, c)]) for c in counters)
+        cells = []
+        for c in counters:
+            vs = agg.get((k, c), [])
+            m = sum(vs) / len(vs) if vs else float("nan")
+            cells.append(f"{m:.4g} ({m / px:.3g})" if c != "SQ_WAVES" else f"{m:.0f}")
+        lines.append(f"| {k} | {n} | " + " | ".join(cells) + " |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def _counter_mean(db, kernel_sub, counter):
     import sqlite3
     con = sqlite3.connect(db)
@@ -561,6 +592,8 @@ def main():
                          "connectivities, ROUNDS times (for a kernel trace) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel over MIB MiB (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("DB", "OUT", "CMD"),
+                    help="write a markdown table of a --pmc run's counters per kernel and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"),
                     help="write a rocprofv3 kernel-trace summary (no GPU needed)")
     ap.add_argument("--summarize-traffic", nargs=7,
@@ -569,6 +602,9 @@ def main():
                     help="write the k_final HBM traffic summary (no GPU needed)")
     args = ap.parse_args()
 
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
         return
