@@ -12,7 +12,7 @@ and 99th percentile (events between steps) and the rate of the library's copy
 kernel (the achievable HBM bandwidth of the device) are reported.
 
 The result is only reported as exact if every image's labels equal the CPU
-checker's (element-by-element, after a warm-up run), which is also timed on
+oracle's (element-by-element, after a warm-up run), which is also timed on
 one host core as the CPU baseline.
 
 Also reported (secondary): the 8192 x 8192 images (Bernoulli p = 0.5 and the
@@ -679,7 +679,7 @@ def main():
         log(f"[bench] profile-stats: {args.profile_stats} rounds of {len(devs)} images")
         return
 
-    # exactness: one labelling of every case, compared with the CPU checker,
+    # exactness: one labelling of every case, compared with the CPU oracle,
     # which is timed on this host's core as the baseline
     exact = True
     cpu = None
@@ -696,7 +696,7 @@ def main():
             cpu_secs += time.perf_counter() - c0
             ok = np.array_equal(got, want)
             exact &= ok
-            log(f"[bench] exact vs checker: {name} conn={conn}: {ok}")
+            log(f"[bench] exact vs oracle: {name} conn={conn}: {ok}")
         os.sched_setaffinity(0, set(range(os.cpu_count() or 1)))
         cpu_px = len(cases) * size * size
         cpu = {"value": round(cpu_px / cpu_secs / 1e9, 5), "unit": "Gpixel/s", "cores": 1,
