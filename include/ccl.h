@@ -194,6 +194,30 @@ int ccl_label_ablation(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_b
 int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
                     int32_t connectivity, int32_t* labels, void* stream);
 
+/*
+ * Launch shape of the two per-tile kernels (the local step and the final
+ * relabel), for callers that tune it (paper_1712_09789_amd/tune.py does):
+ * each runs either as a persistent grid (one workgroup per resident slot,
+ * the next tile's loads in flight while the current one is labelled) or
+ * with one workgroup per tile (the dispatcher balances tiles of unequal
+ * cost).  Labels never depend on the choice.
+ *   batch   0 = calls with one image (ccl_label, ccl_label_stats, ...),
+ *           1 = calls with several (ccl_label_batch, plans, ccl_label_3d)
+ *   bucket  0 .. ccl_launch_buckets() - 1: launches whose total tile count is
+ *           at most the bucket's bound and above the previous one
+ *   local, final_  -1 = the built-in choice (local step per tile beyond four
+ *           times the resident workgroups, final relabel persistent),
+ *           0 = persistent, 1 = one workgroup per tile
+ * Process-wide, applies to launches enqueued afterwards.  CCL_OK, or
+ * CCL_ERR_INVALID_ARG for a value out of range.
+ */
+int ccl_set_launch_policy(int32_t batch, int32_t bucket, int32_t local, int32_t final_);
+
+/* Number of tile-count buckets of ccl_set_launch_policy; writes the first
+ * min(n, buckets) upper bounds (tiles; the last is INT64_MAX) into `upper`
+ * (host memory, may be NULL). */
+int32_t ccl_launch_buckets(int64_t* upper, int32_t n);
+
 /* Tile shape used by the local step (pixels). */
 int32_t ccl_tile_cols(void);
 int32_t ccl_tile_rows(void);

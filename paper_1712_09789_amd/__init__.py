@@ -11,10 +11,11 @@ __all__ = ["ccl", "workloads", "label", "label_batch"]
 
 
 def __getattr__(name):
+    # import_module, not "from . import ccl": the latter asks this module for
+    # the attribute first and would land here again
+    import importlib
     if name in ("label", "label_batch", "label_local"):
-        from . import ccl
-        return getattr(ccl, name)
+        return getattr(importlib.import_module(__name__ + ".ccl"), name)
     if name == "ccl":
-        from . import ccl
-        return ccl
+        return importlib.import_module(__name__ + ".ccl")
     raise AttributeError(name)

@@ -81,10 +81,21 @@ def _load() -> ctypes.CDLL:
     lib.ccl_plan_run.argtypes = [vp, vp]
     lib.ccl_plan_destroy.restype = ctypes.c_int
     lib.ccl_plan_destroy.argtypes = [vp]
+    lib.ccl_set_launch_policy.restype = ctypes.c_int
+    lib.ccl_set_launch_policy.argtypes = [i32, i32, i32, i32]
+    lib.ccl_launch_buckets.restype = i32
+    lib.ccl_launch_buckets.argtypes = [ctypes.POINTER(ctypes.c_int64), i32]
     return lib
 
 
 _lib = _load()
+
+# Launch-shape choices measured by paper_1712_09789_amd.tune on a device of
+# the architecture they name; applied at import when the device matches.
+# CCL_LAUNCH_POLICY names another cache file, or "builtin" to keep the
+# library's built-in choices.
+LAUNCH_POLICY_PATH = os.path.join(_HERE, "launch_policy.json")
+launch_policy_applied: str | None = None
 
 
 def lib() -> ctypes.CDLL:
@@ -94,6 +105,37 @@ def lib() -> ctypes.CDLL:
 def _check(status: int) -> None:
     if status != CCL_OK:
         raise CCLError(status, _lib.ccl_last_error().decode(errors="replace"))
+
+
+def launch_buckets() -> list[int]:
+    """Upper tile-count bound of each launch-policy bucket (the last is
+    2**63 - 1)."""
+    n = _lib.ccl_launch_buckets(None, 0)
+    arr = (ctypes.c_int64 * n)()
+    _lib.ccl_launch_buckets(arr, n)
+    return list(arr)
+
+
+def set_launch_policy(batch: int, bucket: int, local: int, final: int) -> None:
+    """Launch shape of the local step and the final relabel for one launch
+    class (0 = one image, 1 = several) and tile-count bucket: -1 = built-in
+    choice, 0 = persistent grid, 1 = one workgroup per tile (ccl.h)."""
+    _check(_lib.ccl_set_launch_policy(int(batch), int(bucket), int(local), int(final)))
+
+
+def apply_launch_policy(path: str, arch: str | None = None) -> bool:
+    """Apply a cache written by paper_1712_09789_amd.tune; returns False
+    (and changes nothing) if the cache was tuned on another architecture."""
+    import json
+    with open(path) as fh:
+        cache = json.load(fh)
+    if arch is None:
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    if cache.get("arch") != arch:
+        return False
+    for c in cache["choices"]:
+        set_launch_policy(c["batch"], c["bucket"], c["local"], c["final"])
+    return True
 
 
 def _stream_handle(stream) -> int:
@@ -324,3 +366,15 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _apply_packaged_policy() -> None:
+    global launch_policy_applied
+    path = os.environ.get("CCL_LAUNCH_POLICY", LAUNCH_POLICY_PATH)
+    if path == "builtin" or not os.path.exists(path) or not torch.cuda.is_available():
+        return
+    if apply_launch_policy(path):
+        launch_policy_applied = path
+
+
+_apply_packaged_policy()

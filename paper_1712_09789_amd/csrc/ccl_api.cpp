@@ -574,6 +574,22 @@ int ccl_plan_destroy(ccl_plan* plan)
     return CCL_OK;
 }
 
+int ccl_set_launch_policy(int32_t batch, int32_t bucket, int32_t local, int32_t final_)
+{
+    g_err.clear();
+    if (set_launch_policy(batch, bucket, local, final_) != 0)
+        return fail(CCL_ERR_INVALID_ARG,
+                    "ccl_set_launch_policy: batch %d (0|1), bucket %d (0..%d), local %d, final %d "
+                    "(-1|0|1)", batch, bucket, POLICY_BUCKETS - 1, local, final_);
+    return CCL_OK;
+}
+
+int32_t ccl_launch_buckets(int64_t* upper, int32_t n)
+{
+    for (int32_t k = 0; upper && k < n && k < POLICY_BUCKETS; ++k) upper[k] = policy_bucket_bound(k);
+    return POLICY_BUCKETS;
+}
+
 int32_t ccl_tile_cols(void) { return TW; }
 int32_t ccl_tile_rows(void) { return TILE_ROWS; }
 

@@ -189,6 +189,12 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
 // Unite components across adjacent slices of a volume (6- or 26-connectivity)
 // and write canonical labels; the slices' labels must already be in place.
 hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st);
+// Launch shape of k_local / k_final per launch class (batch 0 = one image,
+// 1 = several) and tile-count bucket: -1 = built-in rule, 0 = persistent
+// grid, 1 = one workgroup per tile.  Returns -1 for values out of range.
+constexpr int POLICY_BUCKETS = 5;
+int set_launch_policy(int batch, int bucket, int local, int final_);
+int64_t policy_bucket_bound(int bucket);  // largest tile count of the bucket
 // Writes *count = 0 (an empty image has no components).
 hipError_t launch_zero_count(int64_t* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,

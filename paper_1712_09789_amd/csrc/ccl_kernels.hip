@@ -43,6 +43,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -692,7 +693,7 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
 
 // Each workgroup labels tiles blockIdx.x, +gridDim.x, ... and loads the next
 // tile's bytes while labelling the current one, so that with a grid smaller
-// than the tile count (local_grid) the load latency overlaps the LDS work.
+// than the tile count (tile_grid) the load latency overlaps the LDS work.
 static_assert(TILE_ROWS * 4 == NT, "one sixteen-byte chunk per thread");
 template <int D>
 __global__ __launch_bounds__(NT) void k_local(BatchArgs b, Workspace ws)
@@ -2013,18 +2014,44 @@ static unsigned resident_blocks(K kernel, int threads)
     return n;
 }
 
-// Grid of k_local: persistent (one workgroup per resident slot, the next
-// tile's bytes in flight while the current one is labelled) unless the tiles
-// outnumber the resident workgroups more than four times; then one workgroup
-// per tile, so that the dispatcher balances tiles of unequal cost, which a
-// fixed round-robin over many tiles does not (8192^2: k_local 142 -> 126 us
-// on Bernoulli 0.5, 111 -> 79 us on the spiral).  k_final stays persistent:
-// per tile it gained a little at 8192^2 and lost on batched volume slices.
-static unsigned local_grid(int64_t ntiles, unsigned resident)
+// Launch shape of k_local and k_final: persistent (one workgroup per
+// resident slot, the next tile's loads in flight while the current one is
+// labelled) or one workgroup per tile (the dispatcher balances tiles of
+// unequal cost, which a fixed round-robin over many tiles does not).  A table
+// per launch class (one image / a batch) and tile-count bucket may fix the
+// choice (set by a tuner); otherwise the built-in rule holds: k_local goes
+// per tile beyond four times the resident workgroups (8192^2: 142 -> 126 us
+// on Bernoulli 0.5, 111 -> 79 us on the spiral), k_final stays persistent.
+// Entries hold choice + 1, so zero means the built-in rule.
+static const int64_t kBucketTiles[POLICY_BUCKETS] = {1024, 4096, 16384, 65536, INT64_MAX};
+static std::atomic<int> g_policy[2][POLICY_BUCKETS][2];
+
+static int policy_bucket(int64_t ntiles)
 {
-    return ntiles > 4 * (int64_t)resident ? (unsigned)ntiles
-                                          : (unsigned)std::min<int64_t>(ntiles, resident);
+    int k = 0;
+    while (k < POLICY_BUCKETS - 1 && ntiles > kBucketTiles[k]) ++k;
+    return k;
 }
+
+// kernel 0 = k_local, 1 = k_final
+static unsigned tile_grid(int kernel, const BatchArgs& b, unsigned resident)
+{
+    const int v = g_policy[b.n > 1][policy_bucket(b.ntiles)][kernel].load(std::memory_order_relaxed);
+    const bool per_tile = v ? v == 2 : (kernel == 0 && b.ntiles > 4 * (int64_t)resident);
+    return per_tile ? (unsigned)b.ntiles : (unsigned)std::min<int64_t>(b.ntiles, resident);
+}
+
+int set_launch_policy(int batch, int bucket, int local, int final_)
+{
+    if (batch < 0 || batch > 1 || bucket < 0 || bucket >= POLICY_BUCKETS || local < -1 ||
+        local > 1 || final_ < -1 || final_ > 1)
+        return -1;
+    g_policy[batch][bucket][0].store(local + 1, std::memory_order_relaxed);
+    g_policy[batch][bucket][1].store(final_ + 1, std::memory_order_relaxed);
+    return 0;
+}
+
+int64_t policy_bucket_bound(int bucket) { return kBucketTiles[bucket]; }
 
 int64_t image_groups(int ntx, int nty)
 {
@@ -2046,12 +2073,12 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
 {
     const StatsWs none{};
     if (b.ntiles <= 0) return hipSuccess;
-    const unsigned lgrid = local_grid(b.ntiles, resident_blocks(k_local<D>, NT));
+    const unsigned lgrid = tile_grid(0, b, resident_blocks(k_local<D>, NT));
     timer_begin(timer, KIND_LOCAL, st);
     k_local<D><<<lgrid, NT, 0, st>>>(b, ws);
     timer_end(timer, KIND_LOCAL, st);
     if (local_only) {
-        const unsigned fgrid = (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, true, false>, NT));
+        const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, true, false>, NT));
         timer_begin(timer, KIND_FINAL, st);
         k_final<D, true, false><<<fgrid, NT, 0, st>>>(b, ws, none);
         timer_end(timer, KIND_FINAL, st);
@@ -2069,13 +2096,13 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
         timer_end(timer, KIND_SEAM, st);
     }
     if (!stats) {
-        const unsigned fgrid = (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, false, false>, NT));
+        const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, false, false>, NT));
         timer_begin(timer, KIND_FINAL, st);
         k_final<D, false, false><<<fgrid, NT, 0, st>>>(b, ws, none);
         timer_end(timer, KIND_FINAL, st);
         return hipGetLastError();
     }
-    const unsigned fgrid = (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<D, false, true>, NT));
+    const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, false, true>, NT));
     timer_begin(timer, KIND_FINAL, st);
     k_final<D, false, true><<<fgrid, NT, 0, st>>>(b, ws, *stats);
     timer_end(timer, KIND_FINAL, st);
@@ -2121,7 +2148,7 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
     }
     if (b.ngroups > 0) k_block<0><<<(unsigned)b.ngroups, NTB, 0, st>>>(b, ws);
     if (b.nseamwg > 0) k_seam<0><<<(unsigned)b.nseamwg, SEAM_WG, 0, st>>>(b, ws);
-    const unsigned fgrid = (unsigned)std::min<int64_t>(b.ntiles, resident_blocks(k_final<0, false, false>, NT));
+    const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<0, false, false>, NT));
     k_final<0, false, false><<<fgrid, NT, 0, st>>>(b, ws, StatsWs{});
     return hipGetLastError();
 }

@@ -170,3 +170,24 @@ def test_product_path_does_not_touch_the_oracle():
             if fn.endswith((".py", ".hip", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert not bad.search(text), fn
+
+
+def test_launch_policy_validation(lib):
+    lib.ccl_set_launch_policy.restype = ctypes.c_int
+    lib.ccl_set_launch_policy.argtypes = [ctypes.c_int32] * 4
+    lib.ccl_launch_buckets.restype = ctypes.c_int32
+    lib.ccl_launch_buckets.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.ccl_last_error.restype = ctypes.c_char_p
+    n = lib.ccl_launch_buckets(None, 0)
+    assert n >= 2
+    arr = (ctypes.c_int64 * n)()
+    assert lib.ccl_launch_buckets(ctypes.cast(arr, ctypes.c_void_p), n) == n
+    assert list(arr) == sorted(arr) and arr[n - 1] == (1 << 63) - 1
+    for args in ((2, 0, 0, 0), (-1, 0, 0, 0), (0, n, 0, 0), (0, -1, 0, 0), (0, 0, 2, 0),
+                 (1, 0, 0, -2)):
+        assert lib.ccl_set_launch_policy(*args) == -1, args
+        assert b"ccl_set_launch_policy" in lib.ccl_last_error()
+    for batch in (0, 1):
+        for b in range(n):
+            assert lib.ccl_set_launch_policy(batch, b, 1, 0) == 0
+            assert lib.ccl_set_launch_policy(batch, b, -1, -1) == 0

@@ -4,6 +4,7 @@ Labels are canonical (1 + smallest raster position of the component, 0 for
 background), so the comparison is element-by-element equality: tolerance 0.
 """
 import functools
+import json
 
 import numpy as np
 import pytest
@@ -318,6 +319,70 @@ def test_batch_c4_shapes(ccl):
     torch.cuda.synchronize()
     for i in range(0, 256, 16):
         assert np.array_equal(outs[i].cpu().numpy(), oracle_label(imgs[i], 8)), i
+
+
+def test_launch_policies_same_labels(ccl):
+    """Every launch shape of the local step and the final relabel (persistent
+    or one workgroup per tile) gives the oracle's labels, for single images
+    and batches across tile-count buckets; the tuner's choices are restored
+    afterwards."""
+    bounds = ccl.launch_buckets()
+    singles = [wl.bernoulli(700, 900, 0.55, seed=21), wl.bernoulli(4096, 4096, 0.5, seed=22),
+               wl.blobs(5000, 3000, 4, seed=23)]
+    specs = wl.batch_specs(40, seed=24, lo=16, hi=900)
+    batch = [wl.make(k, H, W, seed=s, **kw) for (H, W, k, kw, s) in specs]
+    want_s = {c: [oracle_label(im, c) for im in singles] for c in (4, 8)}
+    want_b = [oracle_label(im, 8) for im in batch]
+    dsingles = [to_dev(im) for im in singles]
+    dbatch = [to_dev(im) for im in batch]
+    try:
+        for local in (0, 1):
+            for final in (0, 1):
+                for cls in (0, 1):
+                    for b in range(len(bounds)):
+                        ccl.set_launch_policy(cls, b, local, final)
+                for c in (4, 8):
+                    for d, w in zip(dsingles, want_s[c]):
+                        out = ccl.label(d, c)
+                        torch.cuda.synchronize()
+                        assert np.array_equal(out.cpu().numpy(), w), (local, final, c)
+                outs = ccl.label_batch(dbatch, 8)
+                torch.cuda.synchronize()
+                for o, w in zip(outs, want_b):
+                    assert np.array_equal(o.cpu().numpy(), w), (local, final, "batch")
+    finally:
+        for cls in (0, 1):
+            for b in range(len(bounds)):
+                ccl.set_launch_policy(cls, b, -1, -1)
+        if ccl.launch_policy_applied:
+            ccl.apply_launch_policy(ccl.launch_policy_applied)
+
+
+def test_tuner_small_buckets(ccl, tmp_path):
+    """The tuner on the two smallest buckets: one choice per launch class and
+    bucket (an explicit one only where it beat the built-in rule), and labels
+    stay exact with the choices applied."""
+    from paper_1712_09789_amd import tune
+    try:
+        res = tune.tune(reps=2, buckets=[0, 1])
+        assert res["arch"].startswith("gfx")
+        assert len(res["choices"]) == 4
+        for ch in res["choices"]:
+            assert set(ch["us"]) == {"builtin", "0,0", "0,1", "1,0", "1,1"}
+            if ch["local"] >= 0:  # an explicit choice beat the built-in rule
+                t = ch["us"][f"{ch['local']},{ch['final']}"]
+                assert t == min(ch["us"].values()) and t < ch["us"]["builtin"]
+        path = tmp_path / "policy.json"
+        path.write_text(json.dumps(res))
+        assert ccl.apply_launch_policy(str(path))
+        img = wl.bernoulli(1500, 1300, 0.5, seed=31)
+        assert np.array_equal(gpu_label(ccl, img, 8), oracle_label(img, 8))
+    finally:
+        for cls in (0, 1):
+            for b in range(len(ccl.launch_buckets())):
+                ccl.set_launch_policy(cls, b, -1, -1)
+        if ccl.launch_policy_applied:
+            ccl.apply_launch_policy(ccl.launch_policy_applied)
 
 
 def test_plan_and_graph_replay(ccl):
