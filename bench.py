@@ -757,6 +757,9 @@ def main():
         "copy_GBs": round(copy_gbs, 1),
         "path_copy_frac": round(PATH_BYTES_PER_PX * value / copy_gbs, 4),
         "kernel_avg_us": kavg,
+        # launch-shape cache the binding applied (tune.py); None = built-in rule
+        "launch_policy": (os.path.basename(ccl.launch_policy_applied)
+                          if ccl.launch_policy_applied else None),
         # every kernel with algorithmic bytes, against HBM peak (durations from
         # the region with events around every kernel)
         "kernel_hbm": {KERNEL_NAMES[k]: {
