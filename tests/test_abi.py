@@ -191,3 +191,26 @@ def test_launch_policy_validation(lib):
         for b in range(n):
             assert lib.ccl_set_launch_policy(batch, b, 1, 0) == 0
             assert lib.ccl_set_launch_policy(batch, b, -1, -1) == 0
+
+
+def test_launch_policy_cache_loader(tmp_path):
+    """A tuner cache is applied only on the architecture it names, and an
+    out-of-range entry is rejected by the library."""
+    import json
+    import paper_1712_09789_amd.ccl as c
+    n = len(c.launch_buckets())
+    choices = [{"batch": b, "bucket": k, "local": 1, "final": 0} for b in (0, 1) for k in range(n)]
+    path = tmp_path / "policy.json"
+    path.write_text(json.dumps({"arch": "gfxTEST", "choices": choices}))
+    try:
+        assert not c.apply_launch_policy(str(path), arch="gfxOTHER")
+        assert c.apply_launch_policy(str(path), arch="gfxTEST")
+        bad = tmp_path / "bad.json"
+        bad.write_text(json.dumps({"arch": "gfxTEST", "choices": [
+            {"batch": 0, "bucket": n, "local": 0, "final": 0}]}))
+        with pytest.raises(c.CCLError):
+            c.apply_launch_policy(str(bad), arch="gfxTEST")
+    finally:
+        for b in (0, 1):
+            for k in range(n):
+                c.set_launch_policy(b, k, -1, -1)
