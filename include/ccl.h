@@ -131,6 +131,9 @@ typedef struct {
  *   capacity  entries comps holds (>= 0; 0 computes the count only).
  *   count     device int64: the number of components, also when it exceeds
  *             capacity (call again with a larger array to get them all).
+ *             A negative count (-1) reports an internal consistency failure
+ *             found on the device (a label that cannot belong to its pixel);
+ *             the labels and records of that call must not be used.
  * Other arguments and errors as ccl_label; additionally CCL_ERR_INVALID_ARG
  * for a null count, capacity < 0, or a null comps with capacity > 0.  An
  * empty image writes *count = 0.  Enqueued on `stream` like ccl_label.
@@ -225,6 +228,12 @@ int32_t ccl_tile_rows(void);
 /* Workspace bytes one ccl_label call of this size needs (0 for an empty
    image, -1 for invalid sizes). */
 int64_t ccl_workspace_bytes(int32_t H, int32_t W);
+
+/* Bytes of the workspace the library currently keeps for `stream` on the
+   current device (0 if none): it grows to 1.25 x the largest need seen on
+   that stream and is kept until ccl_release_workspace.  For callers that
+   account device memory (a serving loop's admission). */
+int64_t ccl_workspace_cached(void* stream);
 
 /* Thread-local message describing the last non-OK status ("" if none). */
 const char* ccl_last_error(void);

@@ -65,6 +65,8 @@ def _load() -> ctypes.CDLL:
     lib.ccl_tile_rows.restype = i32
     lib.ccl_workspace_bytes.restype = i64
     lib.ccl_workspace_bytes.argtypes = [i32, i32]
+    lib.ccl_workspace_cached.restype = i64
+    lib.ccl_workspace_cached.argtypes = [vp]
     lib.ccl_last_error.restype = ctypes.c_char_p
     lib.ccl_release_workspace.restype = ctypes.c_int
     lib.ccl_release_workspace.argtypes = [i32]
@@ -145,15 +147,20 @@ def _stream_handle(stream) -> int:
 
 
 def _image_args(img: torch.Tensor):
+    """(H, W, pitch in bytes) of a 2-D uint8 image.  Rows must be contiguous
+    and must not overlap (row stride >= W); expanded or overlapping views are
+    rejected here, before anything reaches the device."""
     if img.dim() != 2 or img.dtype != torch.uint8:
         raise ValueError("image must be a 2-D torch.uint8 tensor")
-    if not img.is_cuda:
-        raise ValueError("image must be a device (cuda) tensor")
     H, W = img.shape
     if H > 0 and W > 1 and img.stride(1) != 1:
         raise ValueError("image rows must be contiguous (stride(1) == 1)")
-    pitch = img.stride(0) if H > 1 else W
-    return H, W, max(pitch, W)
+    if H > 1 and W > 0 and img.stride(0) < W:
+        raise ValueError(f"image rows overlap: row stride {img.stride(0)} < width {W} "
+                         "(an expanded or overlapping view; pass a contiguous copy)")
+    if not img.is_cuda:
+        raise ValueError("image must be a device (cuda) tensor")
+    return H, W, (img.stride(0) if H > 1 else W)
 
 
 def _out_for(img: torch.Tensor, out: torch.Tensor | None) -> torch.Tensor:
@@ -210,7 +217,11 @@ def label_stats(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | No
 def components_to_numpy(comps: torch.Tensor, count: torch.Tensor) -> np.ndarray:
     """The valid records of a label_stats result as a numpy structured array
     (synchronises with the device)."""
-    n = min(int(count.item()), comps.numel() // COMPONENT_DTYPE.itemsize)
+    total = int(count.item())
+    if total < 0:
+        raise CCLError(-4, f"ccl_label_stats: the device reported an internal consistency "
+                           f"failure (count {total}); labels and statistics are invalid")
+    n = min(total, comps.numel() // COMPONENT_DTYPE.itemsize)
     raw = comps[:n * COMPONENT_DTYPE.itemsize].cpu().numpy()
     return raw.view(COMPONENT_DTYPE).copy()
 
@@ -221,13 +232,18 @@ def label_3d(vol: torch.Tensor, connectivity: int = 26, out: torch.Tensor | None
     (ccl_label_3d; 6- or 26-connectivity)."""
     if vol.dim() != 3 or vol.dtype != torch.uint8:
         raise ValueError("volume must be a 3-D torch.uint8 tensor")
-    if not vol.is_cuda:
-        raise ValueError("volume must be a device (cuda) tensor")
     D, H, W = vol.shape
     if D > 0 and H > 0 and W > 1 and vol.stride(2) != 1:
         raise ValueError("volume rows must be contiguous (stride(2) == 1)")
-    pitch = max(vol.stride(1) if H > 1 else W, W)
+    pitch = vol.stride(1) if H > 1 else W
+    if H > 1 and W > 0 and pitch < W:
+        raise ValueError(f"volume rows overlap: row stride {pitch} < width {W}")
     slice_pitch = vol.stride(0) if D > 1 else H * pitch
+    if D > 1 and H > 0 and W > 0 and slice_pitch < (H - 1) * pitch + W:
+        raise ValueError(f"volume slices overlap: slice stride {slice_pitch} < "
+                         f"{(H - 1) * pitch + W}")
+    if not vol.is_cuda:
+        raise ValueError("volume must be a device (cuda) tensor")
     if out is None:
         out = torch.empty((D, H, W), dtype=torch.int32, device=vol.device)
     elif out.shape != (D, H, W) or out.dtype != torch.int32 or not out.is_contiguous() \
@@ -298,6 +314,11 @@ def tile_shape() -> tuple[int, int]:
 
 def workspace_bytes(H: int, W: int) -> int:
     return int(_lib.ccl_workspace_bytes(H, W))
+
+
+def workspace_cached(stream=None) -> int:
+    """Bytes of the library workspace kept for `stream` (current device)."""
+    return int(_lib.ccl_workspace_cached(_stream_handle(stream)))
 
 
 def release_workspace(device: int = 0) -> None:

@@ -82,6 +82,61 @@ static int get_workspace(int64_t need, hipStream_t st, void** out)
 }
 
 // ---------------------------------------------------------------------------
+// pinned staging for the batch tables
+// ---------------------------------------------------------------------------
+//
+// The image tables of a batch go to the device with hipMemcpyAsync.  From
+// pageable memory that call waits until the copy has read its source, i.e.
+// until the stream's earlier work is done; from pinned memory it returns at
+// once.  Each (device, stream) keeps a small ring of pinned buffers; a buffer
+// is reused once the event recorded after its last copy has passed (by then
+// normally long ago), so a call never overwrites a table still in flight.
+
+struct Stage {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+constexpr int STAGE_RING = 4;
+struct StageRing {
+    Stage s[STAGE_RING];
+    int next = 0;
+};
+
+static std::mutex g_stage_mu;
+static std::map<std::pair<int, hipStream_t>, StageRing> g_stage;
+
+// Copies `bytes` bytes of `src` to device `dst` on `st` through a pinned
+// buffer; the call does not wait for earlier work on the stream.
+static hipError_t stage_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    StageRing& ring = g_stage[{dev, st}];
+    Stage& b = ring.s[ring.next];
+    ring.next = (ring.next + 1) % STAGE_RING;
+    if (b.used && (e = hipEventSynchronize(b.done)) != hipSuccess) return e;
+    if (b.bytes < bytes) {
+        if (b.host) (void)hipHostFree(b.host);
+        b.host = nullptr;
+        b.bytes = 0;
+        const size_t want = bytes < 65536 ? 65536 : bytes + bytes / 4;
+        if ((e = hipHostMalloc(&b.host, want, hipHostMallocDefault)) != hipSuccess) return e;
+        b.bytes = want;
+    }
+    if (!b.done && (e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess)
+        return e;
+    std::memcpy(b.host, src, bytes);
+    if ((e = hipMemcpyAsync(dst, b.host, bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return e;
+    b.used = true;
+    return hipEventRecord(b.done, st);
+}
+
+// ---------------------------------------------------------------------------
 // event timer
 // ---------------------------------------------------------------------------
 
@@ -250,8 +305,7 @@ static int bind_class(const std::vector<ImageArgs>& imgs, const ClassLayout& L, 
         b.tile_off = dtabs[0];
         b.group_off = dtabs[1];
         b.seam_off = dtabs[2];
-        // pageable source: the copy has read it when the call returns
-        hipError_t e = hipMemcpyAsync(d, h, host.size(), hipMemcpyHostToDevice, st);
+        hipError_t e = stage_copy(d, h, host.size(), st);
         if (e != hipSuccess)
             return fail(CCL_ERR_HIP, "%s: table copy: %s", who, hipGetErrorString(e));
         b.tile_img = reinterpret_cast<int32_t*>(d + o);
@@ -601,6 +655,15 @@ int64_t ccl_workspace_bytes(int32_t H, int32_t W)
     return workspace_bytes(ntiles);
 }
 
+int64_t ccl_workspace_cached(void* stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    const auto it = g_ws.find({dev, static_cast<hipStream_t>(stream)});
+    return it == g_ws.end() ? 0 : it->second.bytes;
+}
+
 const char* ccl_last_error(void) { return g_err.c_str(); }
 
 int ccl_release_workspace(int32_t device)
@@ -623,6 +686,23 @@ int ccl_release_workspace(int32_t device)
             it = g_ws.erase(it);
         } else {
             ++it;
+        }
+    }
+    {
+        // the device is synchronised above if it had a workspace; the staging
+        // buffers' copies are then complete as well
+        std::lock_guard<std::mutex> sl(g_stage_mu);
+        for (auto it = g_stage.begin(); it != g_stage.end();) {
+            if (it->first.first != device) {
+                ++it;
+                continue;
+            }
+            for (Stage& s : it->second.s) {
+                if (s.used) (void)hipEventSynchronize(s.done);
+                if (s.done) (void)hipEventDestroy(s.done);
+                if (s.host) (void)hipHostFree(s.host);
+            }
+            it = g_stage.erase(it);
         }
     }
     if (any) (void)hipSetDevice(prev);

@@ -115,6 +115,10 @@ struct StatRec {
 constexpr int MERGE_FAN = 4;     // a merge workgroup takes the records of 4 x 4 tiles
 constexpr int MERGE_HT = 2048;   // its hash table of distinct components
 
+// Written to the component count by the statistics kernels when a label
+// read back from the label map is impossible for its pixel (see ccl.h).
+constexpr int64_t CCL_STATS_INCONSISTENT = -1;
+
 struct StatsWs {
     uint64_t* rootbits;  // [ntiles][TILE_ROWS] smallest pixels of components, by tile row
     uint32_t* seg;       // [ntiles * TILE_ROWS] per segment: count, then exclusive scan in its block

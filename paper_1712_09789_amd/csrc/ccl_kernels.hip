@@ -1386,7 +1386,13 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         const uint64_t packed = (uint64_t)area | ((uint64_t)sx << 13) | ((uint64_t)sy << 31);
         const int64_t kpos = (int64_t)(gy0 + (int)(key / TW)) * a.W + gx0 + (int)(key % TW);
         const int32_t L = ld_global(a.labels + kpos);
-        if (L <= 0 || (int64_t)L > kpos + 1) continue;  // not a label of this pixel
+        if (L <= 0 || (int64_t)L > kpos + 1) {
+            // a foreground pixel's label is 1 + a position at or before it;
+            // anything else means the labels are wrong: poison the count so
+            // the caller sees the failure instead of missing statistics
+            st_global(st.count, (int64_t)CCL_STATS_INCONSISTENT);
+            continue;
+        }
         const bool is_root = kpos == (int64_t)L - 1;
         const uint32_t en = sh.ent[id];
         const bool border = (en & RT_BORDER) != 0;

@@ -310,15 +310,19 @@ def test_batch_uneven_mixed(ccl, seed):
         assert np.array_equal(outs2[j].cpu().numpy(), outs[i].cpu().numpy())
 
 
-def test_batch_c4_shapes(ccl):
-    """The batched workload's shape mix (256 images, sides log-uniform in
-    [64, 2048]) against the oracle on every 16th image."""
+@pytest.mark.parametrize("conn", [4, 8])
+def test_batch_c4_shapes(ccl, conn):
+    """The batched workload (256 images, sides log-uniform in [64, 2048],
+    Bernoulli and blob content at random density) in one call: every image
+    against the oracle."""
     specs = wl.batch_specs(256, seed=0)
     imgs = [wl.make(k, H, W, seed=s, **kw) for (H, W, k, kw, s) in specs]
-    outs = ccl.label_batch([to_dev(im) for im in imgs], 8)
+    outs = ccl.label_batch([to_dev(im) for im in imgs], conn)
     torch.cuda.synchronize()
-    for i in range(0, 256, 16):
-        assert np.array_equal(outs[i].cpu().numpy(), oracle_label(imgs[i], 8)), i
+    for i in range(256):
+        got = outs[i].cpu().numpy()
+        assert np.array_equal(got, oracle_label(imgs[i], conn)), (i, imgs[i].shape, conn)
+    print(f"[parity] C4 batch conn={conn}: 256 of 256 images exact", flush=True)
 
 
 def test_launch_policies_same_labels(ccl):
