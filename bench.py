@@ -750,7 +750,10 @@ def main():
         "config": {"workload": f"{size}x{size} uint8 single image; Bernoulli p in "
                                "{.1,.3,.5,.7,.9} and median-thresholded blobs sigma {4,16}; "
                                "connectivity 4 and 8; 14 resident buffer sets in rotation",
-                   "tile": list(ccl.tile_shape())},
+                   # tile (rows, cols) the launch policy picks for one image
+                   # of this size, per connectivity
+                   "tile": {f"conn{c}": [ccl.policy_tile_rows(0, size * size, c),
+                                         ccl.tile_shape()[1]] for c in (4, 8)}},
         "step_us": dist,
         "streams_4_Gpx/s": round(streams4, 1) if streams4 else None,
         "path_hbm_frac": round(PATH_BYTES_PER_PX * value / HBM_PEAK_GBS, 4),

@@ -66,6 +66,18 @@ typedef enum {
 int ccl_label(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
               int32_t connectivity, int32_t* labels, void* stream);
 
+/*
+ * ccl_label with an explicit tile height.  The paper's one tuning knob is the
+ * block (tile) shape (Section 4.1, effectiveness of coarse labelling); the
+ * library is built for tiles 64 pixels wide and 32, 64 or 128 rows high, and
+ * ccl_label takes the height from the launch policy (ccl_set_launch_policy).
+ *   tile_rows  32, 64 or 128; 0 = the policy's choice (as ccl_label).
+ * Labels do not depend on the tile height.  Errors as ccl_label, and
+ * CCL_ERR_INVALID_ARG for a height that is not built.
+ */
+int ccl_label_tiled(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                    int32_t connectivity, int32_t* labels, int32_t tile_rows, void* stream);
+
 /* One image of a batch; same meaning as the ccl_label arguments. */
 typedef struct {
     const uint8_t* img;
@@ -85,6 +97,11 @@ typedef struct {
  * identical to labelling each image alone with ccl_label.
  */
 int ccl_label_batch(const ccl_image_desc* descs, int32_t n, void* stream);
+
+/* ccl_label_batch with an explicit tile height for every connectivity class
+ * (32, 64 or 128; 0 = the policy's choice).  Labels do not depend on it. */
+int ccl_label_batch_tiled(const ccl_image_desc* descs, int32_t n, int32_t tile_rows,
+                          void* stream);
 
 /*
  * Prepared batches, for callers that launch the same batch repeatedly (new
@@ -158,8 +175,8 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
  *   labels        device, int32, dense D * H * W; caller-owned, fully
  *                 overwritten.  Must not overlap vol.
  * Errors as ccl_label (CCL_ERR_TOO_LARGE when D * H * W > 2^31 - 1, or when
- * the D slices together have more than (2^31 - 1) / 256 tiles, as very thin
- * slices can); an empty volume is a no-op.
+ * the D slices together have more than (2^31 - 1) / 256 tiles of the built-in
+ * shape, as very thin slices can); an empty volume is a no-op.
  */
 int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pitch_bytes,
                  int64_t slice_pitch_bytes, int32_t connectivity, int32_t* labels, void* stream);
@@ -191,42 +208,62 @@ int ccl_label_ablation(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_b
  * Debugging aid for the local step alone (Section 3.1): every tile is
  * labelled as if it were a separate image, and each foreground pixel gets
  * 1 + the raster position (in the whole image) of the smallest pixel of its
- * component INSIDE its tile.  Tiles are tile_cols() wide and tile_rows()
- * high, aligned at (0, 0).  Same arguments and errors as ccl_label.
+ * component INSIDE its tile.  Tiles are ccl_tile_cols() wide and
+ * ccl_tile_rows() high (the built-in shape), aligned at (0, 0).  Same
+ * arguments and errors as ccl_label.
  */
 int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
                     int32_t connectivity, int32_t* labels, void* stream);
 
 /*
- * Launch shape of the two per-tile kernels (the local step and the final
- * relabel), for callers that tune it (paper_1712_09789_amd/tune.py does):
- * each runs either as a persistent grid (one workgroup per resident slot,
- * the next tile's loads in flight while the current one is labelled) or
- * with one workgroup per tile (the dispatcher balances tiles of unequal
- * cost).  Labels never depend on the choice.
- *   batch   0 = calls with one image (ccl_label, ccl_label_stats, ...),
- *           1 = calls with several (ccl_label_batch, plans, ccl_label_3d)
- *   bucket  0 .. ccl_launch_buckets() - 1: launches whose total tile count is
- *           at most the bucket's bound and above the previous one
- *   local, final_  -1 = the built-in choice (local step per tile beyond four
- *           times the resident workgroups, final relabel persistent),
- *           0 = persistent, 1 = one workgroup per tile
- * Process-wide, applies to launches enqueued afterwards.  CCL_OK, or
+ * Launch policy, for callers that tune it (paper_1712_09789_amd/tune.py
+ * does): per launch class, pixel bucket and connectivity, the tile height
+ * (the paper's block shape, Section 4.1) and the grid of the two per-tile
+ * kernels (the local step and the final relabel).  Each of those runs either
+ * as a persistent grid (one workgroup per resident slot, the next tile's
+ * loads in flight while the current one is labelled) or with one workgroup
+ * per tile (the dispatcher balances tiles of unequal cost).  Labels never
+ * depend on any of these choices.
+ *   batch         0 = calls with one image (ccl_label, plans of one image),
+ *                 1 = calls with several (ccl_label_batch, plans); chosen by
+ *                 the number of non-empty images of one connectivity
+ *   bucket        0 .. ccl_launch_buckets() - 1: launches whose total pixel
+ *                 count (over the images of one connectivity) is at most the
+ *                 bucket's bound and above the previous one
+ *   connectivity  4 or 8
+ *   tile_rows     0 = built-in (64), or 32, 64, 128
+ *   local, final_ -1 = the built-in choice (local step per tile beyond four
+ *                 times the resident workgroups, final relabel persistent),
+ *                 0 = persistent, 1 = one workgroup per tile
+ * ccl_label_stats, ccl_label_3d, ccl_label_ablation and ccl_label_local
+ * always use the built-in tile height and grids.  Process-wide; applies to
+ * launches enqueued (and plans created) afterwards.  CCL_OK, or
  * CCL_ERR_INVALID_ARG for a value out of range.
  */
-int ccl_set_launch_policy(int32_t batch, int32_t bucket, int32_t local, int32_t final_);
+int ccl_set_launch_policy(int32_t batch, int32_t bucket, int32_t connectivity,
+                          int32_t tile_rows, int32_t local, int32_t final_);
 
-/* Number of tile-count buckets of ccl_set_launch_policy; writes the first
- * min(n, buckets) upper bounds (tiles; the last is INT64_MAX) into `upper`
+/* Number of pixel buckets of ccl_set_launch_policy; writes the first
+ * min(n, buckets) upper bounds (pixels; the last is INT64_MAX) into `upper`
  * (host memory, may be NULL). */
 int32_t ccl_launch_buckets(int64_t* upper, int32_t n);
 
-/* Tile shape used by the local step (pixels). */
+/* Tile height the current policy picks for a launch class (0 = one image,
+ * 1 = several) of `pixels` pixels and the given connectivity; -1 for
+ * arguments out of range. */
+int32_t ccl_policy_tile_rows(int32_t batch, int64_t pixels, int32_t connectivity);
+
+/* Number of tile heights built into the library; writes the first min(n,
+ * count) of them (ascending) into `rows` (host memory, may be NULL). */
+int32_t ccl_tile_shapes(int32_t* rows, int32_t n);
+
+/* Built-in tile shape (pixels): 64 columns, 64 rows. */
 int32_t ccl_tile_cols(void);
 int32_t ccl_tile_rows(void);
 
-/* Workspace bytes one ccl_label call of this size needs (0 for an empty
-   image, -1 for invalid sizes). */
+/* Workspace bytes one ccl_label call of this size needs under any tile
+   height (the largest of them; 0 for an empty image, -1 for invalid
+   sizes). */
 int64_t ccl_workspace_bytes(int32_t H, int32_t W);
 
 /* Bytes of the workspace the library currently keeps for `stream` on the

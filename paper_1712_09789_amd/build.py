@@ -27,19 +27,27 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, tile_rows: int | None = None) -> str:
+# Tile heights the kernels are compiled for (one object each; ccl_kernels.h
+# lists the same heights).
+TILE_ROWS = (32, 64, 128)
+
+
+def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    defs = [f"-DCCL_TILE_ROWS={tile_rows}"] if tile_rows else []
-    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"] + defs
-    k_obj = os.path.join(BUILD, "ccl_kernels.o")
+    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
+    objs = []
+    for rows in TILE_ROWS:
+        k_obj = os.path.join(BUILD, f"ccl_kernels_r{rows}.o")
+        _run([hipcc, *common, f"-DCCL_TILE_ROWS={rows}", f"-DCCL_SHAPE_NS=r{rows}",
+              f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c",
+              os.path.join(CSRC, "ccl_kernels.hip"), "-o", k_obj], verbose)
+        objs.append(k_obj)
     a_obj = os.path.join(BUILD, "ccl_api.o")
-    _run([hipcc, *common, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c",
-          os.path.join(CSRC, "ccl_kernels.hip"), "-o", k_obj], verbose)
     _run([hipcc, *common, "-x", "hip", f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c",
           os.path.join(CSRC, "ccl_api.cpp"), "-o", a_obj], verbose)
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, k_obj, a_obj],
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, a_obj],
          verbose)
     os.replace(tmp, LIB)
     return LIB

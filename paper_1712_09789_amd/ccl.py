@@ -59,8 +59,12 @@ def _load() -> ctypes.CDLL:
     lib.ccl_label_3d.argtypes = [vp, i32, i32, i32, i64, i64, i32, vp, vp]
     lib.ccl_label_ablation.restype = ctypes.c_int
     lib.ccl_label_ablation.argtypes = [vp, i32, i32, i64, i32, vp, vp, vp]
+    lib.ccl_label_tiled.restype = ctypes.c_int
+    lib.ccl_label_tiled.argtypes = [vp, i32, i32, i64, i32, vp, i32, vp]
     lib.ccl_label_batch.restype = ctypes.c_int
     lib.ccl_label_batch.argtypes = [ctypes.POINTER(ImageDesc), i32, vp]
+    lib.ccl_label_batch_tiled.restype = ctypes.c_int
+    lib.ccl_label_batch_tiled.argtypes = [ctypes.POINTER(ImageDesc), i32, i32, vp]
     lib.ccl_tile_cols.restype = i32
     lib.ccl_tile_rows.restype = i32
     lib.ccl_workspace_bytes.restype = i64
@@ -84,9 +88,13 @@ def _load() -> ctypes.CDLL:
     lib.ccl_plan_destroy.restype = ctypes.c_int
     lib.ccl_plan_destroy.argtypes = [vp]
     lib.ccl_set_launch_policy.restype = ctypes.c_int
-    lib.ccl_set_launch_policy.argtypes = [i32, i32, i32, i32]
+    lib.ccl_set_launch_policy.argtypes = [i32, i32, i32, i32, i32, i32]
     lib.ccl_launch_buckets.restype = i32
     lib.ccl_launch_buckets.argtypes = [ctypes.POINTER(ctypes.c_int64), i32]
+    lib.ccl_policy_tile_rows.restype = i32
+    lib.ccl_policy_tile_rows.argtypes = [i32, i64, i32]
+    lib.ccl_tile_shapes.restype = i32
+    lib.ccl_tile_shapes.argtypes = [ctypes.POINTER(ctypes.c_int32), i32]
     return lib
 
 
@@ -110,7 +118,7 @@ def _check(status: int) -> None:
 
 
 def launch_buckets() -> list[int]:
-    """Upper tile-count bound of each launch-policy bucket (the last is
+    """Upper pixel-count bound of each launch-policy bucket (the last is
     2**63 - 1)."""
     n = _lib.ccl_launch_buckets(None, 0)
     arr = (ctypes.c_int64 * n)()
@@ -118,11 +126,35 @@ def launch_buckets() -> list[int]:
     return list(arr)
 
 
-def set_launch_policy(batch: int, bucket: int, local: int, final: int) -> None:
-    """Launch shape of the local step and the final relabel for one launch
-    class (0 = one image, 1 = several) and tile-count bucket: -1 = built-in
-    choice, 0 = persistent grid, 1 = one workgroup per tile (ccl.h)."""
-    _check(_lib.ccl_set_launch_policy(int(batch), int(bucket), int(local), int(final)))
+def tile_shapes() -> list[int]:
+    """Tile heights built into the library (tiles are 64 columns wide)."""
+    n = _lib.ccl_tile_shapes(None, 0)
+    arr = (ctypes.c_int32 * n)()
+    _lib.ccl_tile_shapes(arr, n)
+    return list(arr)
+
+
+def set_launch_policy(batch: int, bucket: int, connectivity: int, tile_rows: int = 0,
+                      local: int = -1, final: int = -1) -> None:
+    """Tile height (0 = built-in) and the grids of the local step and the
+    final relabel (-1 = built-in choice, 0 = persistent, 1 = one workgroup
+    per tile) for one launch class (0 = one image, 1 = several), pixel bucket
+    and connectivity (ccl_set_launch_policy in ccl.h)."""
+    _check(_lib.ccl_set_launch_policy(int(batch), int(bucket), int(connectivity),
+                                      int(tile_rows), int(local), int(final)))
+
+
+def reset_launch_policy() -> None:
+    """Every policy entry back to the built-in choices."""
+    for batch in (0, 1):
+        for bucket in range(len(launch_buckets())):
+            for conn in (4, 8):
+                set_launch_policy(batch, bucket, conn)
+
+
+def policy_tile_rows(batch: int, pixels: int, connectivity: int) -> int:
+    """Tile height the current policy picks for a launch class."""
+    return int(_lib.ccl_policy_tile_rows(int(batch), int(pixels), int(connectivity)))
 
 
 def apply_launch_policy(path: str, arch: str | None = None) -> bool:
@@ -136,7 +168,8 @@ def apply_launch_policy(path: str, arch: str | None = None) -> bool:
     if cache.get("arch") != arch:
         return False
     for c in cache["choices"]:
-        set_launch_policy(c["batch"], c["bucket"], c["local"], c["final"])
+        set_launch_policy(c["batch"], c["bucket"], c["connectivity"], c["tile_rows"],
+                          c["local"], c["final"])
     return True
 
 
@@ -175,13 +208,19 @@ def _out_for(img: torch.Tensor, out: torch.Tensor | None) -> torch.Tensor:
 
 
 def label(img: torch.Tensor, connectivity: int = 8, out: torch.Tensor | None = None,
-          stream=None) -> torch.Tensor:
+          stream=None, tile_rows: int = 0) -> torch.Tensor:
     """Canonical connected-component labels of a uint8 device image
-    (0 = background, else 1 + smallest raster position of the component)."""
+    (0 = background, else 1 + smallest raster position of the component).
+    tile_rows: 32, 64 or 128 fixes the tile height (ccl_label_tiled); 0 lets
+    the launch policy choose (ccl_label)."""
     H, W, pitch = _image_args(img)
     out = _out_for(img, out)
-    _check(_lib.ccl_label(img.data_ptr(), H, W, pitch, int(connectivity), out.data_ptr(),
-                          _stream_handle(stream)))
+    if tile_rows:
+        _check(_lib.ccl_label_tiled(img.data_ptr(), H, W, pitch, int(connectivity),
+                                    out.data_ptr(), int(tile_rows), _stream_handle(stream)))
+    else:
+        _check(_lib.ccl_label(img.data_ptr(), H, W, pitch, int(connectivity), out.data_ptr(),
+                              _stream_handle(stream)))
     return out
 
 
@@ -296,19 +335,25 @@ def make_descs(imgs: Sequence[torch.Tensor], outs: Sequence[torch.Tensor],
 
 
 def label_batch(imgs: Sequence[torch.Tensor], connectivity=8,
-                outs: Sequence[torch.Tensor] | None = None, stream=None):
-    """Label several independent images in one call; returns the label tensors."""
+                outs: Sequence[torch.Tensor] | None = None, stream=None, tile_rows: int = 0):
+    """Label several independent images in one call; returns the label
+    tensors.  tile_rows as in label()."""
     if outs is None:
         outs = [_out_for(im, None) for im in imgs]
     else:
         outs = [_out_for(im, o) for im, o in zip(imgs, outs)]
     descs = make_descs(imgs, outs, connectivity)
-    _check(_lib.ccl_label_batch(descs, len(imgs), _stream_handle(stream)))
+    if tile_rows:
+        _check(_lib.ccl_label_batch_tiled(descs, len(imgs), int(tile_rows),
+                                          _stream_handle(stream)))
+    else:
+        _check(_lib.ccl_label_batch(descs, len(imgs), _stream_handle(stream)))
     return list(outs)
 
 
 def tile_shape() -> tuple[int, int]:
-    """(rows, cols) of the local step's tiles."""
+    """(rows, cols) of the built-in tile shape (the statistics, ablation,
+    volume and local-step paths always use it)."""
     return int(_lib.ccl_tile_rows()), int(_lib.ccl_tile_cols())
 
 

@@ -205,17 +205,26 @@ static int validate(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, int
     if (!img || !labels) return fail(CCL_ERR_INVALID_ARG, "%s: null pointer", who);
     if (pitch < W)
         return fail(CCL_ERR_INVALID_ARG, "%s: pitch %lld < width %d", who, (long long)pitch, W);
-    const int64_t ntiles = (int64_t)((W + TW - 1) / TW) * ((H + TILE_ROWS - 1) / TILE_ROWS);
-    if (ntiles * NSLOTS > (int64_t)INT32_MAX)
-        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%d needs too many tiles", who, H, W);
     const uintptr_t i0 = (uintptr_t)img, i1 = i0 + (uintptr_t)((int64_t)(H - 1) * pitch + W);
     const uintptr_t l0 = (uintptr_t)labels, l1 = l0 + (uintptr_t)((int64_t)H * W * 4);
     if (i0 < l1 && l0 < i1) return fail(CCL_ERR_INVALID_ARG, "%s: img and labels overlap", who);
     return CCL_OK;
 }
 
+// Tiles of an H x W image with tiles of `rows` rows.
+static int64_t tiles_of(int32_t H, int32_t W, int rows)
+{
+    return (((int64_t)W + TW - 1) / TW) * (((int64_t)H + rows - 1) / rows);
+}
+
+// Forest node ids (one per border slot of every tile) must fit in int32.
+static bool node_ids_fit(int64_t ntiles, int rows)
+{
+    return ntiles * nslots(rows) <= (int64_t)INT32_MAX;
+}
+
 static ImageArgs make_args(const uint8_t* img, int32_t H, int32_t W, int64_t pitch,
-                           int32_t conn, int32_t* labels)
+                           int32_t* labels, int rows)
 {
     ImageArgs a;
     a.img = img;
@@ -223,9 +232,8 @@ static ImageArgs make_args(const uint8_t* img, int32_t H, int32_t W, int64_t pit
     a.labels = labels;
     a.H = H;
     a.W = W;
-    a.ntx = (W + TW - 1) / TW;
-    a.nty = (H + TILE_ROWS - 1) / TILE_ROWS;
-    (void)conn;  // the launch carries the connectivity (one per batch class)
+    a.ntx = (int32_t)(((int64_t)W + TW - 1) / TW);
+    a.nty = (int32_t)(((int64_t)H + rows - 1) / rows);
     a.unused = 0;
     a.vec_out = ((uintptr_t)labels % 16 == 0) && (W % 4 == 0);
     a.wmagic = W == 1 ? 0xffffffffu : (uint32_t)((1ull << 32) / (uint64_t)W);
@@ -236,19 +244,78 @@ static ImageArgs make_args(const uint8_t* img, int32_t H, int32_t W, int64_t pit
 
 static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
+// ---------------------------------------------------------------------------
+// tile shape and launch grid per call
+// ---------------------------------------------------------------------------
+//
+// A policy entry per (launch class: one image / several, pixel bucket,
+// connectivity) fixes the tile height and the launch grids of k_local and
+// k_final; zero / -1 entries keep the built-in choices (64-row tiles, the
+// kernels' own grid rule).  A tuner (tune.py) measures and sets them.
+
+static const ShapeOps* const kShapes[NSHAPES] = {&r32::ops, &r64::ops, &r128::ops};
+constexpr int POLICY_BUCKETS = 5;
+static const int64_t kBucketPx[POLICY_BUCKETS] = {int64_t(1) << 22, int64_t(1) << 24,
+                                                  int64_t(1) << 26, int64_t(1) << 28, INT64_MAX};
+
+struct PolicyEntry {
+    std::atomic<int> rows{0};  // 0 = built-in (DEFAULT_ROWS)
+    std::atomic<int> local{-1}, final_{-1};
+};
+static PolicyEntry g_policy[2][POLICY_BUCKETS][2];  // [batch][bucket][connectivity == 8]
+
+static int policy_bucket(int64_t px)
+{
+    int k = 0;
+    while (k < POLICY_BUCKETS - 1 && px > kBucketPx[k]) ++k;
+    return k;
+}
+
+static const ShapeOps* shape_for_rows(int rows)
+{
+    for (const ShapeOps* o : kShapes)
+        if (o->rows == rows) return o;
+    return nullptr;
+}
+
+struct Choice {
+    const ShapeOps* ops;
+    GridChoice grid;
+};
+
+// Tile shape and grids for a launch class of `px` pixels; `forced_rows` > 0
+// overrides the policy's tile height (and then the built-in grids hold).
+static Choice choose(bool batch, int64_t px, int conn, int forced_rows)
+{
+    Choice c;
+    if (forced_rows > 0) {
+        c.ops = shape_for_rows(forced_rows);
+        return c;
+    }
+    const PolicyEntry& e = g_policy[batch][policy_bucket(px)][conn == 8];
+    const int rows = e.rows.load(std::memory_order_relaxed);
+    c.ops = shape_for_rows(rows ? rows : DEFAULT_ROWS);
+    c.grid.local = e.local.load(std::memory_order_relaxed);
+    c.grid.final_ = e.final_.load(std::memory_order_relaxed);
+    return c;
+}
+
 // Sizes of one connectivity class of a batch.
 struct ClassLayout {
     int n = 0;
+    int rows = DEFAULT_ROWS;
     std::vector<int64_t> toff, goff, soff;  // prefix offsets (n+1 each)
     int64_t ntiles = 0, ngroups = 0, nseamwg = 0;
     int64_t head = 0;  // bytes of the device tables (0 for a single image)
-    int64_t bytes() const { return head + workspace_bytes(ntiles); }
+    int64_t bytes() const { return head + workspace_bytes(ntiles, rows); }
 };
 
-static int layout_class(std::vector<ImageArgs>& imgs, int conn, ClassLayout& L, const char* who)
+static int layout_class(std::vector<ImageArgs>& imgs, int conn, const ShapeOps& ops,
+                        ClassLayout& L, const char* who)
 {
     const int n = (int)imgs.size();
     L.n = n;
+    L.rows = ops.rows;
     L.toff.assign(n + 1, 0);
     L.goff.assign(n + 1, 0);
     L.soff.assign(n + 1, 0);
@@ -256,14 +323,14 @@ static int layout_class(std::vector<ImageArgs>& imgs, int conn, ClassLayout& L, 
         ImageArgs& a = imgs[i];
         a.tbase = L.toff[i];
         L.toff[i + 1] = L.toff[i] + (int64_t)a.ntx * a.nty;
-        L.goff[i + 1] = L.goff[i] + image_groups(a.ntx, a.nty);
-        const int64_t items = image_seam_items(a.ntx, a.nty, a.H, a.W, conn);
+        L.goff[i + 1] = L.goff[i] + ops.image_groups(a.ntx, a.nty);
+        const int64_t items = ops.image_seam_items(a.ntx, a.nty, a.H, a.W, conn);
         L.soff[i + 1] = L.soff[i] + (items + SEAM_WG - 1) / SEAM_WG;
     }
     L.ntiles = L.toff[n];
     L.ngroups = L.goff[n];
     L.nseamwg = L.soff[n];
-    if (L.ntiles * NSLOTS > (int64_t)INT32_MAX)
+    if (!node_ids_fit(L.ntiles, L.rows))
         return fail(CCL_ERR_TOO_LARGE, "%s: %lld tiles exceed the node id range", who,
                     (long long)L.ntiles);
     L.head = 0;
@@ -314,7 +381,7 @@ static int bind_class(const std::vector<ImageArgs>& imgs, const ClassLayout& L, 
         o += align256(L.ngroups * 4);
         b.seam_img = reinterpret_cast<int32_t*>(d + o);
     }
-    ws = carve_workspace(d + L.head, L.ntiles);
+    ws = carve_workspace(d + L.head, L.ntiles, L.rows);
     return CCL_OK;
 }
 
@@ -330,13 +397,13 @@ struct StatsOut {
 // the head of the workspace) that maps global tiles, merge groups and seam
 // workgroups back to their image.
 
-static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, bool local_only,
-                     const char* who, const StatsOut* so = nullptr, int ablation = -1,
-                     uint32_t* counters = nullptr)
+static int run_batch(std::vector<ImageArgs>& imgs, int conn, const Choice& ch, hipStream_t st,
+                     bool local_only, const char* who, const StatsOut* so = nullptr,
+                     int ablation = -1, uint32_t* counters = nullptr)
 {
     if (imgs.empty()) return CCL_OK;
     ClassLayout L;
-    int rc = layout_class(imgs, conn, L, who);
+    int rc = layout_class(imgs, conn, *ch.ops, L, who);
     if (rc != CCL_OK) return rc;
     const int64_t label_bytes = align256(L.bytes());
     void* base = nullptr;
@@ -353,22 +420,78 @@ static int run_batch(std::vector<ImageArgs>& imgs, int conn, hipStream_t st, boo
         sw.capacity = so->capacity;
         sw.count = so->count;
     }
-    hipError_t e = launch_index(b, st);
+    hipError_t e = ch.ops->index(b, st);
     if (e == hipSuccess && ablation >= 0)
-        e = launch_ablation(b, ws, st, ablation, counters);
+        e = r64::launch_ablation(b, ws, st, ablation, counters);
     else if (e == hipSuccess)
-        e = launch_label(b, conn, ws, st, active_timer(), local_only, so ? &sw : nullptr);
+        e = ch.ops->label(b, conn, ws, st, active_timer(), local_only, ch.grid,
+                          so ? &sw : nullptr);
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
     return CCL_OK;
 }
 
+// One image with the tile shape of `ch`.
 static int label_one(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, int32_t conn,
-                     int32_t* labels, hipStream_t st, bool local_only, const char* who)
+                     int32_t* labels, hipStream_t st, bool local_only, const Choice& ch,
+                     const char* who)
 {
     int rc = validate(img, H, W, pitch, conn, labels, who);
     if (rc != CCL_OK || H == 0 || W == 0) return rc;
-    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch, conn, labels));
-    return run_batch(one, conn, st, local_only, who);
+    if (!node_ids_fit(tiles_of(H, W, ch.ops->rows), ch.ops->rows))
+        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%d needs too many tiles", who, H, W);
+    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch, labels, ch.ops->rows));
+    return run_batch(one, conn, ch, st, local_only, who);
+}
+
+// The built-in tile shape and grids (statistics, ablation, volumes, local step).
+static Choice builtin_choice() { return Choice{&r64::ops, GridChoice{}}; }
+
+// Labels a batch: one set of launches per connectivity class, each with the
+// tile shape the policy (or `forced_rows`) picks for it.
+static int label_batch(const ccl_image_desc* descs, int32_t n, int forced_rows, hipStream_t st,
+                       const char* who)
+{
+    if (n < 0) return fail(CCL_ERR_INVALID_ARG, "%s: n = %d", who, n);
+    if (n == 0) return CCL_OK;
+    if (!descs) return fail(CCL_ERR_INVALID_ARG, "%s: null descriptor array", who);
+    int64_t class_px[2] = {0, 0}, class_n[2] = {0, 0};
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        char w[64];
+        snprintf(w, sizeof w, "%s[%d]", who, i);
+        int rc = validate(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels, w);
+        if (rc != CCL_OK) return rc;
+        if (d.H == 0 || d.W == 0) continue;
+        class_px[d.connectivity == 8] += (int64_t)d.H * d.W;
+        class_n[d.connectivity == 8] += 1;
+    }
+    Choice ch[2];
+    for (int c = 0; c < 2; ++c) ch[c] = choose(class_n[c] > 1, class_px[c], c ? 8 : 4, forced_rows);
+    // the node ids of each connectivity class must fit in int32 (checked
+    // before anything is enqueued)
+    int64_t class_tiles[2] = {0, 0};
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        if (d.H == 0 || d.W == 0) continue;
+        const int c = d.connectivity == 8;
+        class_tiles[c] += tiles_of(d.H, d.W, ch[c].ops->rows);
+    }
+    for (int c = 0; c < 2; ++c)
+        if (class_n[c] && !node_ids_fit(class_tiles[c], ch[c].ops->rows))
+            return fail(CCL_ERR_TOO_LARGE, "%s: %lld tiles of connectivity %d "
+                        "exceed the node id range", who, (long long)class_tiles[c], c ? 8 : 4);
+    std::vector<ImageArgs> by_conn[2];
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        if (d.H == 0 || d.W == 0) continue;
+        const int c = d.connectivity == 8;
+        by_conn[c].push_back(make_args(d.img, d.H, d.W, d.pitch_bytes, d.labels, ch[c].ops->rows));
+    }
+    for (int c = 0; c < 2; ++c) {
+        int rc = run_batch(by_conn[c], c ? 8 : 4, ch[c], st, false, who);
+        if (rc != CCL_OK) return rc;
+    }
+    return CCL_OK;
 }
 
 }  // namespace ccl
@@ -385,6 +508,7 @@ struct ccl_plan {
     void* mem = nullptr;
     struct Class {
         int conn;
+        Choice ch;  // tile shape and grids, fixed when the plan is made
         BatchArgs b;
         Workspace ws;
     };
@@ -397,8 +521,21 @@ int ccl_label(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
               int32_t connectivity, int32_t* labels, void* stream)
 {
     g_err.clear();
+    const Choice ch = choose(false, (int64_t)H * W, connectivity, 0);
     return label_one(img, H, W, pitch_bytes, connectivity, labels,
-                     static_cast<hipStream_t>(stream), false, "ccl_label");
+                     static_cast<hipStream_t>(stream), false, ch, "ccl_label");
+}
+
+int ccl_label_tiled(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                    int32_t connectivity, int32_t* labels, int32_t tile_rows, void* stream)
+{
+    g_err.clear();
+    if (tile_rows != 0 && !shape_for_rows(tile_rows))
+        return fail(CCL_ERR_INVALID_ARG, "ccl_label_tiled: tile height %d is not built "
+                    "(32, 64 or 128; 0 = policy)", tile_rows);
+    const Choice ch = choose(false, (int64_t)H * W, connectivity, tile_rows);
+    return label_one(img, H, W, pitch_bytes, connectivity, labels,
+                     static_cast<hipStream_t>(stream), false, ch, "ccl_label_tiled");
 }
 
 int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
@@ -417,13 +554,15 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
                     (long long)capacity);
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (H == 0 || W == 0) {
-        hipError_t e = launch_zero_count(count, st);
+        hipError_t e = r64::launch_zero_count(count, st);
         if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
         return CCL_OK;
     }
-    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, connectivity, labels));
+    if (!node_ids_fit(tiles_of(H, W, DEFAULT_ROWS), DEFAULT_ROWS))
+        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%d needs too many tiles", who, H, W);
+    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, labels, DEFAULT_ROWS));
     StatsOut so{comps, capacity, count};
-    return run_batch(one, connectivity, st, false, who, &so);
+    return run_batch(one, connectivity, builtin_choice(), st, false, who, &so);
 }
 
 int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pitch_bytes,
@@ -449,21 +588,21 @@ int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pi
                                           (int64_t)(H - 1) * pitch_bytes + W);
     const uintptr_t l0 = (uintptr_t)labels, l1 = l0 + (uintptr_t)((int64_t)D * H * W * 4);
     if (v0 < l1 && l0 < v1) return fail(CCL_ERR_INVALID_ARG, "%s: vol and labels overlap", who);
-    const int64_t tiles = (int64_t)D * ((W + TW - 1) / TW) * ((H + TILE_ROWS - 1) / TILE_ROWS);
-    if (tiles * NSLOTS > (int64_t)INT32_MAX)
+    const int64_t tiles = (int64_t)D * tiles_of(H, W, DEFAULT_ROWS);
+    if (!node_ids_fit(tiles, DEFAULT_ROWS))
         return fail(CCL_ERR_TOO_LARGE, "%s: %lld tiles over all slices exceed the node id range",
                     who, (long long)tiles);
     const int conn2 = connectivity == 6 ? 4 : 8;  // the in-slice part of the neighbourhood
     std::vector<ImageArgs> slices;
     slices.reserve(D);
     for (int32_t z = 0; z < D; ++z) {
-        ImageArgs a = make_args(vol + (int64_t)z * slice_pitch_bytes, H, W, pitch_bytes, conn2,
-                                labels + (int64_t)z * H * W);
+        ImageArgs a = make_args(vol + (int64_t)z * slice_pitch_bytes, H, W, pitch_bytes,
+                                labels + (int64_t)z * H * W, DEFAULT_ROWS);
         a.lbase = (int32_t)((int64_t)z * H * W);
         slices.push_back(a);
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int rc = run_batch(slices, conn2, st, false, who);
+    int rc = run_batch(slices, conn2, builtin_choice(), st, false, who);
     if (rc != CCL_OK) return rc;
     VolArgs v;
     v.labels = labels;
@@ -471,7 +610,7 @@ int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pi
     v.H = H;
     v.W = W;
     v.vec = ((uintptr_t)labels & 15) == 0;
-    hipError_t e = launch_volume(v, connectivity, st);
+    hipError_t e = r64::launch_volume(v, connectivity, st);
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
     return CCL_OK;
 }
@@ -485,9 +624,11 @@ int ccl_label_ablation(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_b
         return fail(CCL_ERR_INVALID_ARG, "%s: variant %d is not one of 0..3", who, variant);
     int rc = validate(img, H, W, pitch_bytes, 4, labels, who);
     if (rc != CCL_OK || H == 0 || W == 0) return rc;
-    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, 4, labels));
-    return run_batch(one, 4, static_cast<hipStream_t>(stream), false, who, nullptr, variant,
-                     counters);
+    if (!node_ids_fit(tiles_of(H, W, DEFAULT_ROWS), DEFAULT_ROWS))
+        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%d needs too many tiles", who, H, W);
+    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, labels, DEFAULT_ROWS));
+    return run_batch(one, 4, builtin_choice(), static_cast<hipStream_t>(stream), false, who,
+                     nullptr, variant, counters);
 }
 
 int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
@@ -495,48 +636,24 @@ int ccl_label_local(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
 {
     g_err.clear();
     return label_one(img, H, W, pitch_bytes, connectivity, labels,
-                     static_cast<hipStream_t>(stream), true, "ccl_label_local");
+                     static_cast<hipStream_t>(stream), true, builtin_choice(), "ccl_label_local");
 }
 
 int ccl_label_batch(const ccl_image_desc* descs, int32_t n, void* stream)
 {
     g_err.clear();
-    if (n < 0) return fail(CCL_ERR_INVALID_ARG, "ccl_label_batch: n = %d", n);
-    if (n == 0) return CCL_OK;
-    if (!descs) return fail(CCL_ERR_INVALID_ARG, "ccl_label_batch: null descriptor array");
-    for (int32_t i = 0; i < n; ++i) {
-        const ccl_image_desc& d = descs[i];
-        char who[64];
-        snprintf(who, sizeof who, "ccl_label_batch[%d]", i);
-        int rc = validate(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels, who);
-        if (rc != CCL_OK) return rc;
-    }
-    // the node ids of each connectivity class must fit in int32 (checked
-    // before anything is enqueued)
-    int64_t class_tiles[2] = {0, 0};
-    for (int32_t i = 0; i < n; ++i) {
-        const ccl_image_desc& d = descs[i];
-        class_tiles[d.connectivity == 8] +=
-            (int64_t)((d.W + TW - 1) / TW) * ((d.H + TILE_ROWS - 1) / TILE_ROWS);
-    }
-    for (int c = 0; c < 2; ++c)
-        if (class_tiles[c] * NSLOTS > (int64_t)INT32_MAX)
-            return fail(CCL_ERR_TOO_LARGE, "ccl_label_batch: %lld tiles of connectivity %d "
-                        "exceed the node id range", (long long)class_tiles[c], c ? 8 : 4);
-    // one set of launches per connectivity
-    std::vector<ImageArgs> by_conn[2];
-    for (int32_t i = 0; i < n; ++i) {
-        const ccl_image_desc& d = descs[i];
-        if (d.H == 0 || d.W == 0) continue;
-        by_conn[d.connectivity == 8].push_back(
-            make_args(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels));
-    }
-    for (int c = 0; c < 2; ++c) {
-        int rc = run_batch(by_conn[c], c ? 8 : 4, static_cast<hipStream_t>(stream), false,
-                           "ccl_label_batch");
-        if (rc != CCL_OK) return rc;
-    }
-    return CCL_OK;
+    return label_batch(descs, n, 0, static_cast<hipStream_t>(stream), "ccl_label_batch");
+}
+
+int ccl_label_batch_tiled(const ccl_image_desc* descs, int32_t n, int32_t tile_rows,
+                          void* stream)
+{
+    g_err.clear();
+    if (tile_rows != 0 && !shape_for_rows(tile_rows))
+        return fail(CCL_ERR_INVALID_ARG, "ccl_label_batch_tiled: tile height %d is not built "
+                    "(32, 64 or 128; 0 = policy)", tile_rows);
+    return label_batch(descs, n, tile_rows, static_cast<hipStream_t>(stream),
+                       "ccl_label_batch_tiled");
 }
 
 int ccl_plan_create(const ccl_image_desc* descs, int32_t n, void* stream, ccl_plan** plan)
@@ -546,7 +663,7 @@ int ccl_plan_create(const ccl_image_desc* descs, int32_t n, void* stream, ccl_pl
     *plan = nullptr;
     if (n < 0 || (n > 0 && !descs)) return fail(CCL_ERR_INVALID_ARG, "ccl_plan_create: bad descriptors");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    std::vector<ImageArgs> by_conn[2];
+    int64_t class_px[2] = {0, 0}, class_n[2] = {0, 0};
     for (int32_t i = 0; i < n; ++i) {
         const ccl_image_desc& d = descs[i];
         char who[64];
@@ -554,14 +671,23 @@ int ccl_plan_create(const ccl_image_desc* descs, int32_t n, void* stream, ccl_pl
         int rc = validate(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels, who);
         if (rc != CCL_OK) return rc;
         if (d.H == 0 || d.W == 0) continue;
-        by_conn[d.connectivity == 8].push_back(
-            make_args(d.img, d.H, d.W, d.pitch_bytes, d.connectivity, d.labels));
+        class_px[d.connectivity == 8] += (int64_t)d.H * d.W;
+        class_n[d.connectivity == 8] += 1;
+    }
+    Choice ch[2];
+    for (int c = 0; c < 2; ++c) ch[c] = choose(class_n[c] > 1, class_px[c], c ? 8 : 4, 0);
+    std::vector<ImageArgs> by_conn[2];
+    for (int32_t i = 0; i < n; ++i) {
+        const ccl_image_desc& d = descs[i];
+        if (d.H == 0 || d.W == 0) continue;
+        const int c = d.connectivity == 8;
+        by_conn[c].push_back(make_args(d.img, d.H, d.W, d.pitch_bytes, d.labels, ch[c].ops->rows));
     }
     ClassLayout L[2];
     int64_t total = 0;
     for (int c = 0; c < 2; ++c) {
         if (by_conn[c].empty()) continue;
-        int rc = layout_class(by_conn[c], c ? 8 : 4, L[c], "ccl_plan_create");
+        int rc = layout_class(by_conn[c], c ? 8 : 4, *ch[c].ops, L[c], "ccl_plan_create");
         if (rc != CCL_OK) return rc;
         total += align256(L[c].bytes());
     }
@@ -581,8 +707,9 @@ int ccl_plan_create(const ccl_image_desc* descs, int32_t n, void* stream, ccl_pl
         if (by_conn[c].empty()) continue;
         ccl_plan::Class k;
         k.conn = c ? 8 : 4;
+        k.ch = ch[c];
         int rc = bind_class(by_conn[c], L[c], base, false, st, k.b, k.ws, "ccl_plan_create");
-        hipError_t e = rc == CCL_OK ? launch_index(k.b, st) : hipSuccess;
+        hipError_t e = rc == CCL_OK ? k.ch.ops->index(k.b, st) : hipSuccess;
         if (rc != CCL_OK || e != hipSuccess) {
             (void)hipStreamSynchronize(st);
             (void)hipFree(p->mem);
@@ -608,7 +735,8 @@ int ccl_plan_run(ccl_plan* plan, void* stream)
     if (!plan) return fail(CCL_ERR_INVALID_ARG, "ccl_plan_run: null plan");
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (auto& k : plan->classes) {
-        hipError_t e = launch_label(k.b, k.conn, k.ws, st, active_timer(), false);
+        hipError_t e = k.ch.ops->label(k.b, k.conn, k.ws, st, active_timer(), false, k.ch.grid,
+                                       nullptr);
         if (e != hipSuccess) return fail(CCL_ERR_HIP, "ccl_plan_run: %s", hipGetErrorString(e));
     }
     return CCL_OK;
@@ -628,31 +756,56 @@ int ccl_plan_destroy(ccl_plan* plan)
     return CCL_OK;
 }
 
-int ccl_set_launch_policy(int32_t batch, int32_t bucket, int32_t local, int32_t final_)
+int ccl_set_launch_policy(int32_t batch, int32_t bucket, int32_t connectivity,
+                          int32_t tile_rows, int32_t local, int32_t final_)
 {
     g_err.clear();
-    if (set_launch_policy(batch, bucket, local, final_) != 0)
+    if (batch < 0 || batch > 1 || bucket < 0 || bucket >= POLICY_BUCKETS ||
+        (connectivity != 4 && connectivity != 8) || (tile_rows != 0 && !shape_for_rows(tile_rows)) ||
+        local < -1 || local > 1 || final_ < -1 || final_ > 1)
         return fail(CCL_ERR_INVALID_ARG,
-                    "ccl_set_launch_policy: batch %d (0|1), bucket %d (0..%d), local %d, final %d "
-                    "(-1|0|1)", batch, bucket, POLICY_BUCKETS - 1, local, final_);
+                    "ccl_set_launch_policy: batch %d (0|1), bucket %d (0..%d), connectivity %d "
+                    "(4|8), tile rows %d (0|32|64|128), local %d, final %d (-1|0|1)",
+                    batch, bucket, POLICY_BUCKETS - 1, connectivity, tile_rows, local, final_);
+    PolicyEntry& e = g_policy[batch][bucket][connectivity == 8];
+    e.rows.store(tile_rows, std::memory_order_relaxed);
+    e.local.store(local, std::memory_order_relaxed);
+    e.final_.store(final_, std::memory_order_relaxed);
     return CCL_OK;
 }
 
 int32_t ccl_launch_buckets(int64_t* upper, int32_t n)
 {
-    for (int32_t k = 0; upper && k < n && k < POLICY_BUCKETS; ++k) upper[k] = policy_bucket_bound(k);
+    for (int32_t k = 0; upper && k < n && k < POLICY_BUCKETS; ++k) upper[k] = kBucketPx[k];
     return POLICY_BUCKETS;
 }
 
+int32_t ccl_policy_tile_rows(int32_t batch, int64_t pixels, int32_t connectivity)
+{
+    if (batch < 0 || batch > 1 || pixels < 0 || (connectivity != 4 && connectivity != 8))
+        return -1;
+    return choose(batch == 1, pixels, connectivity, 0).ops->rows;
+}
+
+int32_t ccl_tile_shapes(int32_t* rows, int32_t n)
+{
+    for (int32_t k = 0; rows && k < n && k < NSHAPES; ++k) rows[k] = SHAPE_ROWS[k];
+    return NSHAPES;
+}
+
 int32_t ccl_tile_cols(void) { return TW; }
-int32_t ccl_tile_rows(void) { return TILE_ROWS; }
+int32_t ccl_tile_rows(void) { return DEFAULT_ROWS; }
 
 int64_t ccl_workspace_bytes(int32_t H, int32_t W)
 {
     if (H < 0 || W < 0) return -1;
     if (H == 0 || W == 0) return 0;
-    const int64_t ntiles = (int64_t)((W + TW - 1) / TW) * ((H + TILE_ROWS - 1) / TILE_ROWS);
-    return workspace_bytes(ntiles);
+    int64_t most = 0;
+    for (const ShapeOps* o : kShapes) {
+        const int64_t b = workspace_bytes(tiles_of(H, W, o->rows), o->rows);
+        most = b > most ? b : most;
+    }
+    return most;
 }
 
 int64_t ccl_workspace_cached(void* stream)
@@ -755,7 +908,8 @@ int ccl_copy_bytes(const void* src, void* dst, int64_t bytes, void* stream)
     if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)bytes) % 16)
         return fail(CCL_ERR_INVALID_ARG, "ccl_copy_bytes: pointers and size must be 16-byte aligned");
     if (bytes == 0) return CCL_OK;
-    hipError_t e = launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream), active_timer());
+    hipError_t e =
+        r64::launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream), active_timer());
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "ccl_copy_bytes: %s", hipGetErrorString(e));
     return CCL_OK;
 }

@@ -1,4 +1,10 @@
 // Internal interface between the host library and the HIP kernels.
+//
+// The kernels are compiled once per tile height (ccl_kernels.hip built with
+// -DCCL_TILE_ROWS=<rows> -DCCL_SHAPE_NS=r<rows>); each build exports its
+// launchers through a ShapeOps table, and the host picks a tile shape per
+// call.  Everything in this header that depends on the tile height takes it
+// as an argument.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,12 +16,18 @@ namespace ccl {
 // row in the local kernels.
 constexpr int TW = 64;
 
-#ifndef CCL_TILE_ROWS
-#define CCL_TILE_ROWS 64
-#endif
-constexpr int TILE_ROWS = CCL_TILE_ROWS;
-constexpr int NSLOTS = 2 * TW + 2 * TILE_ROWS;  // border pixels per tile
-constexpr int RUNTAB_PER_TILE = TILE_ROWS * TW / 2;  // run-table entries per tile
+// Tile heights built into the library, and the built-in choice.  The
+// statistics, ablation and volume paths always use the built-in height.
+constexpr int NSHAPES = 3;
+constexpr int SHAPE_ROWS[NSHAPES] = {32, 64, 128};
+constexpr int DEFAULT_ROWS = 64;
+
+// Border pixels per tile (top row, bottom row, left column, right column).
+constexpr int nslots(int rows) { return 2 * TW + 2 * rows; }
+// Run-table entries per tile: one per run, at most one run per two columns.
+constexpr int runtab_per_tile(int rows) { return rows * TW / 2; }
+// Threads of a tile workgroup: one sixteen-pixel chunk of a row each.
+constexpr int tile_threads(int rows) { return 4 * rows; }
 
 struct ImageArgs {
     const uint8_t* img;
@@ -60,33 +72,35 @@ struct BatchArgs {
 
 // Device workspace of one image.
 struct Workspace {
-    uint64_t* bits;    // [ntiles][TILE_ROWS] foreground masks
-    int32_t* slots;    // [ntiles][NSLOTS] forest node of each border pixel, -1 = bg
-    uint64_t* forest;  // [ntiles][NSLOTS] (key of parent << 32) | parent node
-    uint16_t* runtab;  // [ntiles][RUNTAB_PER_TILE] local root of each run
+    uint64_t* bits;    // [ntiles][rows] foreground masks
+    int32_t* slots;    // [ntiles][nslots] forest node of each border pixel, -1 = bg
+    uint64_t* forest;  // [ntiles][nslots] (key of parent << 32) | parent node
+    uint16_t* runtab;  // [ntiles][runtab_per_tile] local root of each run
     uint32_t* nruns;   // [ntiles] runs of each tile (valid run-table entries)
 };
 
-inline int64_t workspace_bytes(int64_t ntiles)
+inline int64_t workspace_bytes(int64_t ntiles, int rows)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
-    return up(ntiles * TILE_ROWS * 8) + up(ntiles * NSLOTS * 4) + up(ntiles * NSLOTS * 8) +
-           up(ntiles * RUNTAB_PER_TILE * 2) + up(ntiles * 4);
+    const int64_t ns = nslots(rows);
+    return up(ntiles * rows * 8) + up(ntiles * ns * 4) + up(ntiles * ns * 8) +
+           up(ntiles * runtab_per_tile(rows) * 2) + up(ntiles * 4);
 }
 
-inline Workspace carve_workspace(void* base, int64_t ntiles)
+inline Workspace carve_workspace(void* base, int64_t ntiles, int rows)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    const int64_t ns = nslots(rows);
     char* p = static_cast<char*>(base);
     Workspace ws;
     ws.bits = reinterpret_cast<uint64_t*>(p);
-    p += up(ntiles * TILE_ROWS * 8);
+    p += up(ntiles * rows * 8);
     ws.slots = reinterpret_cast<int32_t*>(p);
-    p += up(ntiles * NSLOTS * 4);
+    p += up(ntiles * ns * 4);
     ws.forest = reinterpret_cast<uint64_t*>(p);
-    p += up(ntiles * NSLOTS * 8);
+    p += up(ntiles * ns * 8);
     ws.runtab = reinterpret_cast<uint16_t*>(p);
-    p += up(ntiles * RUNTAB_PER_TILE * 2);
+    p += up(ntiles * runtab_per_tile(rows) * 2);
     ws.nruns = reinterpret_cast<uint32_t*>(p);
     return ws;
 }
@@ -99,10 +113,11 @@ struct CompStats {
     int64_t sum_x, sum_y;
 };
 
-// Statistics workspace and outputs of one image.  Components are numbered in
-// raster order of their smallest pixel: the count of such pixels per
-// (image row, tile column) segment is scanned, and a component's number is
-// the scanned count of its segment plus the smallest pixels left of it there.
+// Statistics workspace and outputs of one image (tiles of DEFAULT_ROWS
+// rows).  Components are numbered in raster order of their smallest pixel:
+// the count of such pixels per (image row, tile column) segment is scanned,
+// and a component's number is the scanned count of its segment plus the
+// smallest pixels left of it there.
 constexpr int SCAN_T = 1024;                // scan workgroup size
 constexpr int SCAN_BLK = 4 * SCAN_T;        // segments per first-level scan block
 // Partial statistics of one component over part of the image, in global
@@ -120,11 +135,11 @@ constexpr int MERGE_HT = 2048;   // its hash table of distinct components
 constexpr int64_t CCL_STATS_INCONSISTENT = -1;
 
 struct StatsWs {
-    uint64_t* rootbits;  // [ntiles][TILE_ROWS] smallest pixels of components, by tile row
-    uint32_t* seg;       // [ntiles * TILE_ROWS] per segment: count, then exclusive scan in its block
+    uint64_t* rootbits;  // [ntiles][rows] smallest pixels of components, by tile row
+    uint32_t* seg;       // [ntiles * rows] per segment: count, then exclusive scan in its block
     uint32_t* bsum;      // [nblk] segments' total per scan block
     uint32_t* boff;      // [nblk] exclusive scan of bsum
-    StatRec* rec0;       // [ntiles][NSLOTS] per tile: partials of its border components
+    StatRec* rec0;       // [ntiles][nslots] per tile: partials of its border components
     uint32_t* cnt0;      // [ntiles]
     int64_t nseg, nblk;
     int32_t g1x, g1y;    // grid of merge workgroups (4 x 4 tiles each)
@@ -136,9 +151,9 @@ struct StatsWs {
 inline int64_t stats_workspace_bytes(int64_t ntiles)
 {
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
-    const int64_t nseg = ntiles * TILE_ROWS, nblk = (nseg + SCAN_BLK - 1) / SCAN_BLK;
+    const int64_t nseg = ntiles * DEFAULT_ROWS, nblk = (nseg + SCAN_BLK - 1) / SCAN_BLK;
     return up(nseg * 8) + up(nseg * 4) + 2 * up(nblk * 4) +
-           up(ntiles * NSLOTS * (int64_t)sizeof(StatRec)) + up(ntiles * 4);
+           up(ntiles * nslots(DEFAULT_ROWS) * (int64_t)sizeof(StatRec)) + up(ntiles * 4);
 }
 
 inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
@@ -146,7 +161,7 @@ inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     char* p = static_cast<char*>(base);
     StatsWs s{};
-    s.nseg = ntiles * TILE_ROWS;
+    s.nseg = ntiles * DEFAULT_ROWS;
     s.nblk = (s.nseg + SCAN_BLK - 1) / SCAN_BLK;
     s.g1x = (ntx + MERGE_FAN - 1) / MERGE_FAN;
     s.g1y = (nty + MERGE_FAN - 1) / MERGE_FAN;
@@ -159,7 +174,7 @@ inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
     s.boff = reinterpret_cast<uint32_t*>(p);
     p += up(s.nblk * 4);
     s.rec0 = reinterpret_cast<StatRec*>(p);
-    p += up(ntiles * NSLOTS * (int64_t)sizeof(StatRec));
+    p += up(ntiles * nslots(DEFAULT_ROWS) * (int64_t)sizeof(StatRec));
     s.cnt0 = reinterpret_cast<uint32_t*>(p);
     return s;
 }
@@ -173,18 +188,39 @@ struct KernelTimer;  // host-side event recorder, null when timing is off
 void timer_begin(KernelTimer* t, int kind, hipStream_t st);
 void timer_end(KernelTimer* t, int kind, hipStream_t st);
 
-// Tile-grid quantities of one image, shared by the host and the launchers.
-int64_t image_groups(int ntx, int nty);      // merge groups
-int64_t image_seam_items(int ntx, int nty, int H, int W, int conn);  // k_seam work items
-constexpr int SEAM_WG = 256;                 // k_seam workgroup size
+constexpr int SEAM_WG = 256;  // k_seam workgroup size
 
-// k_index: fills the image-of-tile/group/seam-workgroup tables of a batch
-// (n > 1); must precede launch_label on the same stream.
-hipError_t launch_index(const BatchArgs& b, hipStream_t st);
-// With `stats` (a single image only) k_final also records the smallest
-// pixels of components, and the statistics kernels follow it.
-hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
-                        KernelTimer* timer, bool local_only, const StatsWs* stats = nullptr);
+// Launch grid of k_local and k_final: -1 = built-in rule, 0 = persistent (one
+// workgroup per resident slot), 1 = one workgroup per tile.
+struct GridChoice {
+    int local = -1;
+    int final_ = -1;
+};
+
+// Launchers and tile-grid quantities of one tile-height build.
+struct ShapeOps {
+    int rows;
+    int64_t (*image_groups)(int ntx, int nty);  // merge groups of an image
+    int64_t (*image_seam_items)(int ntx, int nty, int H, int W, int conn);  // k_seam work items
+    // k_index: fills the image-of-tile/group/seam-workgroup tables of a
+    // batch (n > 1); must precede label on the same stream.
+    hipError_t (*index)(const BatchArgs& b, hipStream_t st);
+    // With `stats` (a single image, DEFAULT_ROWS build only) k_final also
+    // records the smallest pixels of components, and the statistics kernels
+    // follow it.
+    hipError_t (*label)(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
+                        KernelTimer* timer, bool local_only, GridChoice grid,
+                        const StatsWs* stats);
+};
+
+namespace r32 {
+extern const ShapeOps ops;
+}
+namespace r128 {
+extern const ShapeOps ops;
+}
+namespace r64 {
+extern const ShapeOps ops;
 // The local step's ablation variants (0 = rows and columns, 1 = rows only,
 // 2 = columns only, 3 = none), 4-connectivity, a single image, followed by
 // the usual merge and final kernels; `counters` (2 per tile) may be null.
@@ -193,15 +229,10 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
 // Unite components across adjacent slices of a volume (6- or 26-connectivity)
 // and write canonical labels; the slices' labels must already be in place.
 hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st);
-// Launch shape of k_local / k_final per launch class (batch 0 = one image,
-// 1 = several) and tile-count bucket: -1 = built-in rule, 0 = persistent
-// grid, 1 = one workgroup per tile.  Returns -1 for values out of range.
-constexpr int POLICY_BUCKETS = 5;
-int set_launch_policy(int batch, int bucket, int local, int final_);
-int64_t policy_bucket_bound(int bucket);  // largest tile count of the bucket
 // Writes *count = 0 (an empty image has no components).
 hipError_t launch_zero_count(int64_t* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,
                        KernelTimer* timer);
+}  // namespace r64
 
 }  // namespace ccl

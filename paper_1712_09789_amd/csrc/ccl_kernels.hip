@@ -2,7 +2,10 @@
 //
 // The image is cut into tiles of 64 x TILE_ROWS pixels: one 64-bit
 // foreground mask per tile row, so the paper's row scan becomes bit
-// arithmetic on a word.  A workgroup of 256 threads owns a tile.
+// arithmetic on a word.  A workgroup of 4 * TILE_ROWS threads owns a tile
+// (one sixteen-pixel chunk of a row each).  The file is compiled once per
+// tile height (32, 64 and 128 rows: the paper's block shape is its tuning
+// knob), and the host picks the height per call.
 //
 // Nodes of the tile-local union-find are runs: maximal horizontal stretches
 // of foreground.  Under 8-connectivity two rows are fused into a strip first:
@@ -17,7 +20,7 @@
 //            table (local root of each run), one forest node id per border
 //            pixel, and one forest node per component that touches the tile
 //            border.
-//   k_block  (Section 3.2, inside groups of 4 x 4 tiles)  unite the border
+//   k_block  (Section 3.2, inside groups of 256 x 256 pixels)  unite the border
 //            nodes across the seams inside the group in LDS and write the
 //            group roots to the forest.
 //   k_seam   (Section 3.2, between groups)  for every foreground pair
@@ -50,9 +53,24 @@
 
 #include "ccl_kernels.h"
 
-namespace ccl {
+// One build per tile height: CCL_TILE_ROWS rows, launchers in namespace
+// ccl::CCL_SHAPE_NS.
+#ifndef CCL_TILE_ROWS
+#define CCL_TILE_ROWS 64
+#endif
+#ifndef CCL_SHAPE_NS
+#define CCL_SHAPE_NS r64
+#endif
 
-constexpr int NT = 256;  // threads per tile workgroup
+namespace ccl {
+namespace CCL_SHAPE_NS {
+
+constexpr int TILE_ROWS = CCL_TILE_ROWS;
+static_assert(TILE_ROWS == 32 || TILE_ROWS == 64 || TILE_ROWS == 128, "built tile heights");
+constexpr int NSLOTS = nslots(TILE_ROWS);             // border pixels per tile
+constexpr int RUNTAB_PER_TILE = runtab_per_tile(TILE_ROWS);
+constexpr int NT = tile_threads(TILE_ROWS);           // threads per tile workgroup
+constexpr int SPT = (NSLOTS + NT - 1) / NT;           // border slots per thread, at most
 
 // Geometry of one connectivity: D = 0 (4-connectivity, lines are rows) or
 // D = 1 (8-connectivity, lines are two-row strips).
@@ -67,7 +85,8 @@ struct Geo {
     static constexpr int MAXE = NL * (D ? TW : TW / 2);
 };
 static_assert(Geo<0>::MAXR <= RUNTAB_PER_TILE && Geo<1>::MAXR <= RUNTAB_PER_TILE, "run table");
-static_assert(NSLOTS == NT, "one border slot per thread");
+// packed LDS parents hold a 16-bit tile key and a 16-bit run id
+static_assert(TILE_ROWS * TW <= 0x8000 && Geo<0>::MAXR <= 0x10000, "16-bit keys and ids");
 
 // ---------------------------------------------------------------------------
 // bit helpers
@@ -305,24 +324,37 @@ template <int D>
 __device__ void build_lines(Lines<D>& sh, int tid)
 {
     constexpr int NL = Geo<D>::NL;
+    constexpr int LPL = (NL + 63) / 64;  // consecutive lines per lane of the first wavefront
     if (tid < 64) {
-        uint32_t cnt = 0;
-        if (tid < NL) {
-            const uint64_t lm = D ? (sh.M[2 * tid] | sh.M[2 * tid + 1]) : sh.M[tid];
-            const uint64_t ls = lm & ~(lm << 1);
-            sh.LM[tid] = lm;
-            sh.LS[tid] = ls;
-            cnt = popc64(ls);
+        uint32_t cnt[LPL], tot = 0;
+#pragma unroll
+        for (int k = 0; k < LPL; ++k) {
+            const int l = tid * LPL + k;
+            cnt[k] = 0;
+            if (l < NL) {
+                const uint64_t lm = D ? (sh.M[2 * l] | sh.M[2 * l + 1]) : sh.M[l];
+                const uint64_t ls = lm & ~(lm << 1);
+                sh.LM[l] = lm;
+                sh.LS[l] = ls;
+                cnt[k] = popc64(ls);
+            }
+            tot += cnt[k];
         }
         // inclusive scan of the run counts across the first wavefront
-        uint32_t inc = cnt;
+        uint32_t inc = tot;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t o = __shfl_up(inc, off, 64);
             if (tid >= off) inc += o;
         }
-        if (tid < NL) sh.base[tid] = inc - cnt;
-        if (tid == NL - 1) sh.base[NL] = inc;
+        uint32_t run = inc - tot;
+#pragma unroll
+        for (int k = 0; k < LPL; ++k) {
+            const int l = tid * LPL + k;
+            if (l < NL) sh.base[l] = run;
+            run += cnt[k];
+        }
+        if (tid == 63) sh.base[NL] = inc;
     }
     __syncthreads();
 }
@@ -638,36 +670,49 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
     for (uint32_t id = tid; id < R; id += NT) lds_st(sh.P + id, pfind(sh.P, id));
     __syncthreads();
 
-    // Border slots (one per thread): local root of each border pixel.
-    const int s = tid;
-    int sx, sy;
-    slot_xy(s, sx, sy);
-    const bool fg = (sh.M[sy] >> sx) & 1ull;
-    uint32_t root = 0, rkey = 0;
-    if (fg) {
-        const uint32_t v = lds_ld(sh.P + run_id<D>(sh, D ? sy >> 1 : sy, sx));
-        root = pk_id(v);
-        rkey = pk_key(v);
+    // Border slots (slots tid, tid + NT, ...): local root of each border pixel.
+    bool fg[SPT];
+    uint32_t root[SPT], rkey[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int s = tid + k * NT;
+        fg[k] = false;
+        root[k] = rkey[k] = 0;
+        if (s < NSLOTS) {
+            int sx, sy;
+            slot_xy(s, sx, sy);
+            fg[k] = (sh.M[sy] >> sx) & 1ull;
+            if (fg[k]) {
+                const uint32_t v = lds_ld(sh.P + run_id<D>(sh, D ? sy >> 1 : sy, sx));
+                root[k] = pk_id(v);
+                rkey[k] = pk_key(v);
+            }
+        }
     }
     __syncthreads();
     // Elect the smallest slot of each border component as its representative
     // (an atomic max on the root entry, which is no longer needed as a parent).
-    if (fg)
-        __hip_atomic_fetch_max(sh.P + root, REP_TAG | (uint32_t)(NSLOTS - 1 - s),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+        if (fg[k])
+            __hip_atomic_fetch_max(sh.P + root[k], REP_TAG | (uint32_t)(NSLOTS - 1 - (tid + k * NT)),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
 
     // ID conversion (Section 3.1.4): the representative's forest node carries
     // the raster position of the component's smallest pixel.
     const int64_t sbase = T * NSLOTS;
-    {
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int s = tid + k * NT;
+        if (s >= NSLOTS) continue;
         int32_t node = -1;
-        if (fg) {
-            const int rep = NSLOTS - 1 - (int)pk_id(lds_ld(sh.P + root));
+        if (fg[k]) {
+            const int rep = NSLOTS - 1 - (int)pk_id(lds_ld(sh.P + root[k]));
             node = (int32_t)(sbase + rep);
             if (rep == s) {
-                const uint32_t gkey = (uint32_t)((int64_t)(gy0 + (int)(rkey / TW)) * a.W +
-                                                 gx0 + (int)(rkey % TW));
+                const uint32_t gkey = (uint32_t)((int64_t)(gy0 + (int)(rkey[k] / TW)) * a.W +
+                                                 gx0 + (int)(rkey[k] % TW));
                 ws.forest[node] = ((uint64_t)gkey << 32) | (uint32_t)node;
             }
         }
@@ -751,7 +796,8 @@ __global__ __launch_bounds__(NT) void k_local(BatchArgs b, Workspace ws)
 // sides repeat.  Node ids are unique across tiles, so a covering edge always
 // joins the same two tiles as the edge it covers.
 
-constexpr int BX = 4, BY = 4;                    // tiles per merge group
+// tiles per merge group: a group is 256 x 256 pixels for every tile height
+constexpr int BX = 4, BY = 256 / TILE_ROWS;
 constexpr int BPX = BX * TW, BPY = BY * TILE_ROWS;  // group size in pixels
 constexpr int BN = BX * BY * NSLOTS;             // border slots per group
 static_assert(BPX * BPY <= 65536 && BN <= 65536, "16-bit group keys and ids");
@@ -1034,19 +1080,22 @@ struct FinalShared : Lines<D> {
 static_assert(RUNTAB_PER_TILE == 8 * NT, "one 16-byte run-table load per thread");
 
 struct FinalFetch {
-    int32_t node;
+    int32_t node[SPT];
     uint32_t nruns;
     uint64_t m;
 };
 
-// Loads of one tile for k_final that depend on no other: the border slot of
-// this thread, the row masks and the run count (which sizes the run-table
-// load issued when the tile's turn comes).
+// Loads of one tile for k_final that depend on no other: the border slots of
+// this thread (tid, tid + NT, ...), the row masks and the run count (which
+// sizes the run-table load issued when the tile's turn comes).
 __device__ __forceinline__ FinalFetch final_fetch(const Workspace& ws, int64_t T, int tid)
 {
-    static_assert(NSLOTS == NT, "one border slot per thread");
     FinalFetch f;
-    f.node = ws.slots[T * NSLOTS + tid];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int s = tid + k * NT;
+        f.node[k] = s < NSLOTS ? ws.slots[T * NSLOTS + s] : -1;
+    }
     f.nruns = ws.nruns[T];
     f.m = tid < TILE_ROWS ? ws.bits[T * TILE_ROWS + tid] : 0ull;
     return f;
@@ -1072,7 +1121,9 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
     uint4 ent = make_uint4(0u, 0u, 0u, 0u);
     if (8u * tid < f.nruns)
         ent = reinterpret_cast<const uint4*>(ws.runtab + T * RUNTAB_PER_TILE)[tid];
-    uint64_t v = f.node >= 0 ? ws.forest[f.node] : 0;
+    uint64_t v[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) v[k] = f.node[k] >= 0 ? ws.forest[f.node[k]] : 0;
     if (tid < TILE_ROWS) {
         sh.M[tid] = f.m;
         if (STATS) sh.rb[tid] = 0ull;
@@ -1081,28 +1132,32 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
     build_lines<D>(sh, tid);
     const uint32_t R = sh.base[Geo<D>::NL];
     reinterpret_cast<uint4*>(sh.ent)[tid] = ent;
-    // Global root of the component at this border slot.  The slot names a
-    // forest node of that component (its tile representative, or the group
-    // root after the block merge); before any merge the node is the root.
-    if (f.node >= 0) {
+    // Global root of the component at each of this thread's border slots.
+    // The slot names a forest node of that component (its tile
+    // representative, or the group root after the block merge); before any
+    // merge the node is the root.
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        if (f.node[k] < 0) continue;
+        uint64_t vk = v[k];
         if (!LOCAL_ONLY) {
             // The merge is over, so every node's root is fixed and any
             // ancestor is a valid parent: beyond the first hop (whose node
             // the whole group's tiles share) the path is halved with plain
             // stores, which keeps later chases short on images whose merge
             // left long chains (one component snaking through many groups).
-            uint32_t n = (uint32_t)f.node;
+            uint32_t n = (uint32_t)f.node[k];
             bool first = true;
-            while ((uint32_t)v != n) {
-                const uint32_t p = (uint32_t)v;
+            while ((uint32_t)vk != n) {
+                const uint32_t p = (uint32_t)vk;
                 const uint64_t vp = ld_global(ws.forest + p);
                 if (!first && (uint32_t)vp != p) st_global(ws.forest + n, vp);
                 first = false;
                 n = p;
-                v = vp;
+                vk = vp;
             }
         }
-        sh.fin[tid] = (int32_t)((uint32_t)(v >> 32) + 1u) + a.lbase;
+        sh.fin[tid + k * NT] = (int32_t)((uint32_t)(vk >> 32) + 1u) + a.lbase;
     }
     __syncthreads();
     for (uint32_t id = tid; id < R; id += NT) {
@@ -1198,6 +1253,11 @@ __global__ __launch_bounds__(NT) void k_final(BatchArgs b, Workspace ws, StatsWs
         __syncthreads();
     }
 }
+
+// The statistics, ablation, volume and copy kernels are built only with the
+// built-in tile height (their host entry points always use it).
+#if CCL_TILE_ROWS == 64
+static_assert(NSLOTS == NT, "one border slot per thread in the statistics and ablation kernels");
 
 // ---------------------------------------------------------------------------
 // per-component statistics
@@ -1992,6 +2052,8 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
         dst[i] = src[i];
 }
 
+#endif  // CCL_TILE_ROWS == 64
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -2023,41 +2085,18 @@ static unsigned resident_blocks(K kernel, int threads)
 // Launch shape of k_local and k_final: persistent (one workgroup per
 // resident slot, the next tile's loads in flight while the current one is
 // labelled) or one workgroup per tile (the dispatcher balances tiles of
-// unequal cost, which a fixed round-robin over many tiles does not).  A table
-// per launch class (one image / a batch) and tile-count bucket may fix the
-// choice (set by a tuner); otherwise the built-in rule holds: k_local goes
-// per tile beyond four times the resident workgroups (8192^2: 142 -> 126 us
-// on Bernoulli 0.5, 111 -> 79 us on the spiral), k_final stays persistent.
-// Entries hold choice + 1, so zero means the built-in rule.
-static const int64_t kBucketTiles[POLICY_BUCKETS] = {1024, 4096, 16384, 65536, INT64_MAX};
-static std::atomic<int> g_policy[2][POLICY_BUCKETS][2];
-
-static int policy_bucket(int64_t ntiles)
-{
-    int k = 0;
-    while (k < POLICY_BUCKETS - 1 && ntiles > kBucketTiles[k]) ++k;
-    return k;
-}
-
+// unequal cost, which a fixed round-robin over many tiles does not).  The
+// caller may fix the choice (a tuned policy); otherwise the built-in rule
+// holds: k_local goes per tile beyond four times the resident workgroups
+// (8192^2 with 64-row tiles: 142 -> 126 us on Bernoulli 0.5, 111 -> 79 us on
+// the spiral), k_final stays persistent.
 // kernel 0 = k_local, 1 = k_final
-static unsigned tile_grid(int kernel, const BatchArgs& b, unsigned resident)
+static unsigned tile_grid(int kernel, const BatchArgs& b, unsigned resident, GridChoice g)
 {
-    const int v = g_policy[b.n > 1][policy_bucket(b.ntiles)][kernel].load(std::memory_order_relaxed);
-    const bool per_tile = v ? v == 2 : (kernel == 0 && b.ntiles > 4 * (int64_t)resident);
+    const int v = kernel == 0 ? g.local : g.final_;
+    const bool per_tile = v >= 0 ? v == 1 : (kernel == 0 && b.ntiles > 4 * (int64_t)resident);
     return per_tile ? (unsigned)b.ntiles : (unsigned)std::min<int64_t>(b.ntiles, resident);
 }
-
-int set_launch_policy(int batch, int bucket, int local, int final_)
-{
-    if (batch < 0 || batch > 1 || bucket < 0 || bucket >= POLICY_BUCKETS || local < -1 ||
-        local > 1 || final_ < -1 || final_ > 1)
-        return -1;
-    g_policy[batch][bucket][0].store(local + 1, std::memory_order_relaxed);
-    g_policy[batch][bucket][1].store(final_ + 1, std::memory_order_relaxed);
-    return 0;
-}
-
-int64_t policy_bucket_bound(int bucket) { return kBucketTiles[bucket]; }
 
 int64_t image_groups(int ntx, int nty)
 {
@@ -2075,16 +2114,20 @@ int64_t image_seam_items(int ntx, int nty, int H, int W, int conn)
 
 template <int D>
 static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_t st,
-                             KernelTimer* timer, bool local_only, const StatsWs* stats)
+                             KernelTimer* timer, bool local_only, GridChoice grid,
+                             const StatsWs* stats)
 {
     const StatsWs none{};
     if (b.ntiles <= 0) return hipSuccess;
-    const unsigned lgrid = tile_grid(0, b, resident_blocks(k_local<D>, NT));
+#if CCL_TILE_ROWS != 64
+    if (stats) return hipErrorInvalidValue;  // statistics use the built-in tile height
+#endif
+    const unsigned lgrid = tile_grid(0, b, resident_blocks(k_local<D>, NT), grid);
     timer_begin(timer, KIND_LOCAL, st);
     k_local<D><<<lgrid, NT, 0, st>>>(b, ws);
     timer_end(timer, KIND_LOCAL, st);
     if (local_only) {
-        const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, true, false>, NT));
+        const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, true, false>, NT), grid);
         timer_begin(timer, KIND_FINAL, st);
         k_final<D, true, false><<<fgrid, NT, 0, st>>>(b, ws, none);
         timer_end(timer, KIND_FINAL, st);
@@ -2102,13 +2145,15 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
         timer_end(timer, KIND_SEAM, st);
     }
     if (!stats) {
-        const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, false, false>, NT));
+        const unsigned fgrid =
+            tile_grid(1, b, resident_blocks(k_final<D, false, false>, NT), grid);
         timer_begin(timer, KIND_FINAL, st);
         k_final<D, false, false><<<fgrid, NT, 0, st>>>(b, ws, none);
         timer_end(timer, KIND_FINAL, st);
         return hipGetLastError();
     }
-    const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, false, true>, NT));
+#if CCL_TILE_ROWS == 64
+    const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<D, false, true>, NT), grid);
     timer_begin(timer, KIND_FINAL, st);
     k_final<D, false, true><<<fgrid, NT, 0, st>>>(b, ws, *stats);
     timer_end(timer, KIND_FINAL, st);
@@ -2123,6 +2168,7 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
             *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, stats->g1x, a.W, a.H);
     }
     timer_end(timer, KIND_STATS, st);
+#endif
     return hipGetLastError();
 }
 
@@ -2135,12 +2181,19 @@ hipError_t launch_index(const BatchArgs& b, hipStream_t st)
 }
 
 hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
-                        KernelTimer* timer, bool local_only, const StatsWs* stats)
+                        KernelTimer* timer, bool local_only, GridChoice grid,
+                        const StatsWs* stats)
 {
-    if (conn == 8) return launch_all<1>(b, ws, st, timer, local_only, stats);
-    return launch_all<0>(b, ws, st, timer, local_only, stats);
+    if (conn == 8) return launch_all<1>(b, ws, st, timer, local_only, grid, stats);
+    return launch_all<0>(b, ws, st, timer, local_only, grid, stats);
 }
 
+// The launcher table is host data (the device pass does not see it).
+#if !defined(__HIP_DEVICE_COMPILE__)
+const ShapeOps ops = {TILE_ROWS, image_groups, image_seam_items, launch_index, launch_label};
+#endif
+
+#if CCL_TILE_ROWS == 64
 hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t st, int variant,
                            uint32_t* counters)
 {
@@ -2154,7 +2207,8 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
     }
     if (b.ngroups > 0) k_block<0><<<(unsigned)b.ngroups, NTB, 0, st>>>(b, ws);
     if (b.nseamwg > 0) k_seam<0><<<(unsigned)b.nseamwg, SEAM_WG, 0, st>>>(b, ws);
-    const unsigned fgrid = tile_grid(1, b, resident_blocks(k_final<0, false, false>, NT));
+    const unsigned fgrid =
+        tile_grid(1, b, resident_blocks(k_final<0, false, false>, NT), GridChoice{});
     k_final<0, false, false><<<fgrid, NT, 0, st>>>(b, ws, StatsWs{});
     return hipGetLastError();
 }
@@ -2192,5 +2246,7 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
     timer_end(timer, KIND_COPY, st);
     return hipGetLastError();
 }
+#endif  // CCL_TILE_ROWS == 64
 
+}  // namespace CCL_SHAPE_NS
 }  // namespace ccl

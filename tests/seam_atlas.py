@@ -77,24 +77,26 @@ def expected_labels(rel_rows: np.ndarray, y0: np.ndarray, x0: np.ndarray, W: int
 
 
 def sites(H, W, rows, cols, G):
-    """Top-left corners of the pattern sites, by class."""
+    """Top-left corners of the pattern sites, by class.  G = tiles per merge
+    group side, or (tiles per group column, tiles per group row)."""
+    GY, GX = (G, G) if isinstance(G, int) else G
     out = {}
     nty, ntx = H // rows, W // cols
     # corners of four tiles
     for k in range(1, nty):
         for i in range(1, ntx):
-            out.setdefault(("corner", k % G, i % G), []).append((k * rows - 2, i * cols - 2))
+            out.setdefault(("corner", k % GY, i % GX), []).append((k * rows - 2, i * cols - 2))
     # along vertical seams, between the corner patterns (gap row on each side)
     along_v = list(range(3, rows - SIDE - 3, STEP_ALONG))
     along_h = list(range(3, cols - SIDE - 3, STEP_ALONG))
     for i in range(1, ntx):
         for k in range(nty):
             for r in along_v:
-                out.setdefault(("vseam", i % G), []).append((k * rows + r, i * cols - 2))
+                out.setdefault(("vseam", i % GX), []).append((k * rows + r, i * cols - 2))
     for k in range(1, nty):
         for i in range(ntx):
             for c in along_h:
-                out.setdefault(("hseam", k % G), []).append((k * rows - 2, i * cols + c))
+                out.setdefault(("hseam", k % GY), []).append((k * rows - 2, i * cols + c))
     return {key: np.array(v, np.int64) for key, v in out.items()}
 
 

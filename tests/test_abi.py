@@ -148,10 +148,33 @@ def test_batch_validation(lib):
 def test_sizes_and_shape(lib):
     import paper_1712_09789_amd.ccl as c
     rows, cols = c.tile_shape()
-    assert cols == 64 and rows in (16, 32, 64, 128, 256)
+    assert (rows, cols) == (64, 64)
+    assert c.tile_shapes() == [32, 64, 128]
     assert c.workspace_bytes(0, 10) == 0
     assert c.workspace_bytes(-1, 10) == -1
     assert c.workspace_bytes(8192, 8192) > 0
+    # the largest need over the tile heights: 32-row tiles have the most
+    # border slots per pixel
+    assert c.workspace_bytes(1000, 1000) >= c.workspace_bytes(1000, 999)
+
+
+def test_tiled_entry_points_validate(lib):
+    import paper_1712_09789_amd.ccl as c
+    L = c.lib()
+    for rows in (1, 16, 48, 96, 256, -32):
+        assert L.ccl_label_tiled(FAKE_IMG, 4, 4, 4, 8, FAKE_OUT, rows, None) == -1, rows
+        assert b"tile height" in L.ccl_last_error()
+        descs = (c.ImageDesc * 1)()
+        descs[0] = c.ImageDesc(FAKE_IMG, 4, 4, 4, 8, FAKE_OUT)
+        assert L.ccl_label_batch_tiled(descs, 1, rows, None) == -1, rows
+    # argument errors are found before any launch, whatever the height
+    for rows in (0, 32, 64, 128):
+        assert L.ccl_label_tiled(FAKE_IMG, 4, 4, 3, 8, FAKE_OUT, rows, None) == -1
+        assert L.ccl_label_tiled(FAKE_IMG, 4, 4, 4, 6, FAKE_OUT, rows, None) == -1
+        assert L.ccl_label_tiled(FAKE_IMG, 0, 4, 4, 8, FAKE_OUT, rows, None) == 0
+        # one pixel row per tile row of a 2^31-wide image: too many tiles
+        assert L.ccl_label_tiled(FAKE_IMG, 1, (1 << 31) - 1, (1 << 31) - 1, 8,
+                                 FAKE_OUT + (1 << 33), rows, None) == -2
 
 
 def test_copy_validation(lib):
@@ -173,24 +196,32 @@ def test_product_path_does_not_touch_the_oracle():
 
 
 def test_launch_policy_validation(lib):
-    lib.ccl_set_launch_policy.restype = ctypes.c_int
-    lib.ccl_set_launch_policy.argtypes = [ctypes.c_int32] * 4
-    lib.ccl_launch_buckets.restype = ctypes.c_int32
-    lib.ccl_launch_buckets.argtypes = [ctypes.c_void_p, ctypes.c_int32]
-    lib.ccl_last_error.restype = ctypes.c_char_p
-    n = lib.ccl_launch_buckets(None, 0)
+    import paper_1712_09789_amd.ccl as c
+    L = c.lib()
+    n = L.ccl_launch_buckets(None, 0)
     assert n >= 2
     arr = (ctypes.c_int64 * n)()
-    assert lib.ccl_launch_buckets(ctypes.cast(arr, ctypes.c_void_p), n) == n
+    assert L.ccl_launch_buckets(arr, n) == n
     assert list(arr) == sorted(arr) and arr[n - 1] == (1 << 63) - 1
-    for args in ((2, 0, 0, 0), (-1, 0, 0, 0), (0, n, 0, 0), (0, -1, 0, 0), (0, 0, 2, 0),
-                 (1, 0, 0, -2)):
-        assert lib.ccl_set_launch_policy(*args) == -1, args
-        assert b"ccl_set_launch_policy" in lib.ccl_last_error()
-    for batch in (0, 1):
-        for b in range(n):
-            assert lib.ccl_set_launch_policy(batch, b, 1, 0) == 0
-            assert lib.ccl_set_launch_policy(batch, b, -1, -1) == 0
+    for args in ((2, 0, 8, 0, 0, 0), (-1, 0, 8, 0, 0, 0), (0, n, 8, 0, 0, 0),
+                 (0, -1, 8, 0, 0, 0), (0, 0, 6, 0, 0, 0), (0, 0, 8, 48, 0, 0),
+                 (0, 0, 8, 0, 2, 0), (1, 0, 4, 0, 0, -2)):
+        assert L.ccl_set_launch_policy(*args) == -1, args
+        assert b"ccl_set_launch_policy" in L.ccl_last_error()
+    try:
+        for batch in (0, 1):
+            for b in range(n):
+                for conn in (4, 8):
+                    for rows in (32, 64, 128):
+                        assert L.ccl_set_launch_policy(batch, b, conn, rows, 1, 0) == 0
+                        px = arr[b] if b < n - 1 else arr[n - 2] + 1
+                        assert c.policy_tile_rows(batch, px, conn) == rows
+                    assert L.ccl_set_launch_policy(batch, b, conn, 0, -1, -1) == 0
+                    assert c.policy_tile_rows(batch, arr[0], conn) == 64
+        assert c.policy_tile_rows(2, 100, 8) == -1
+        assert c.policy_tile_rows(0, 100, 5) == -1
+    finally:
+        c.reset_launch_policy()
 
 
 def test_launch_policy_cache_loader(tmp_path):
@@ -199,18 +230,37 @@ def test_launch_policy_cache_loader(tmp_path):
     import json
     import paper_1712_09789_amd.ccl as c
     n = len(c.launch_buckets())
-    choices = [{"batch": b, "bucket": k, "local": 1, "final": 0} for b in (0, 1) for k in range(n)]
+    choices = [{"batch": b, "bucket": k, "connectivity": conn, "tile_rows": 128, "local": 1,
+                "final": 0} for b in (0, 1) for k in range(n) for conn in (4, 8)]
     path = tmp_path / "policy.json"
     path.write_text(json.dumps({"arch": "gfxTEST", "choices": choices}))
     try:
         assert not c.apply_launch_policy(str(path), arch="gfxOTHER")
+        assert c.policy_tile_rows(0, 1000, 8) == 64
         assert c.apply_launch_policy(str(path), arch="gfxTEST")
+        assert c.policy_tile_rows(0, 1000, 8) == 128
+        assert c.policy_tile_rows(1, 1 << 40, 4) == 128
         bad = tmp_path / "bad.json"
         bad.write_text(json.dumps({"arch": "gfxTEST", "choices": [
-            {"batch": 0, "bucket": n, "local": 0, "final": 0}]}))
+            {"batch": 0, "bucket": 0, "connectivity": 8, "tile_rows": 96, "local": 0,
+             "final": 0}]}))
         with pytest.raises(c.CCLError):
             c.apply_launch_policy(str(bad), arch="gfxTEST")
     finally:
-        for b in (0, 1):
-            for k in range(n):
-                c.set_launch_policy(b, k, -1, -1)
+        c.reset_launch_policy()
+
+
+def test_packaged_policy_is_well_formed():
+    """The packaged cache names an architecture, one entry per (class,
+    bucket, connectivity), and only heights and grids the library accepts."""
+    import json
+    import paper_1712_09789_amd.ccl as c
+    with open(c.LAUNCH_POLICY_PATH) as fh:
+        cache = json.load(fh)
+    assert cache["arch"].startswith("gfx")
+    n = len(c.launch_buckets())
+    keys = {(e["batch"], e["bucket"], e["connectivity"]) for e in cache["choices"]}
+    assert keys == {(b, k, conn) for b in (0, 1) for k in range(n) for conn in (4, 8)}
+    for e in cache["choices"]:
+        assert e["tile_rows"] in (0, 32, 64, 128)
+        assert e["local"] in (-1, 0, 1) and e["final"] in (-1, 0, 1)

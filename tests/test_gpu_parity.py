@@ -73,11 +73,19 @@ def test_geometries(ccl, kind, kw, H, W, conn):
     assert_parity(ccl, wl.make(kind, H, W, **kw), conn, kind)
 
 
+def tiled_parity(ccl, img, conn, rows, what):
+    got = ccl.label(to_dev(img), conn, tile_rows=rows)
+    torch.cuda.synchronize()
+    want = oracle_label(img, conn)
+    assert np.array_equal(got.cpu().numpy(), want), (what, rows, conn, img.shape)
+
+
+@pytest.mark.parametrize("rows", [32, 64, 128])
 @pytest.mark.parametrize("conn", [4, 8])
-def test_seam_patterns(ccl, conn):
+def test_seam_patterns(ccl, conn, rows):
     """Random 4x4 patterns centred on every kind of seam position: a vertical
     seam, a horizontal seam and a four-tile corner, in one image per trial."""
-    rows, cols = ccl.tile_shape()
+    cols = ccl.tile_shape()[1]
     rng = np.random.default_rng(conn)
     H, W = 3 * rows, 3 * cols
     for trial in range(40):
@@ -85,16 +93,17 @@ def test_seam_patterns(ccl, conn):
         for cy, cx in [(rows // 2, cols), (rows, cols // 2), (rows, cols),
                        (2 * rows, 2 * cols), (rows, 2 * cols), (2 * rows, cols)]:
             img[cy - 2:cy + 2, cx - 2:cx + 2] = rng.random((4, 4)) < 0.5
-        assert_parity(ccl, img, conn, f"seam trial {trial}")
+        tiled_parity(ccl, img, conn, rows, f"seam trial {trial}")
 
 
+@pytest.mark.parametrize("rows", [32, 64, 128])
 @pytest.mark.parametrize("conn", [4, 8])
-def test_group_seam_patterns(ccl, conn):
+def test_group_seam_patterns(ccl, conn, rows):
     """Random 4x4 patterns on every kind of seam of a multi-group image: tile
-    seams, seams between merge groups (every 4 tiles), group corners, and the
-    diagonals that cross a group column on a tile seam inside a group."""
-    rows, cols = ccl.tile_shape()
-    gr, gc = 4 * rows, 4 * cols
+    seams, seams between merge groups (every 256 pixels), group corners, and
+    the diagonals that cross a group column on a tile seam inside a group."""
+    cols = ccl.tile_shape()[1]
+    gr, gc = 256, 256
     rng = np.random.default_rng(100 + conn)
     H, W = 2 * gr + 3 * rows, 2 * gc + 2 * cols + 5
     centres = [(y, x) for y in range(rows, H, rows) for x in range(cols, W, cols)]
@@ -102,15 +111,16 @@ def test_group_seam_patterns(ccl, conn):
         img = (rng.random((H, W)) < 0.04).astype(np.uint8)
         for cy, cx in centres:
             img[cy - 2:cy + 2, cx - 2:cx + 2] = rng.random((4, 4)) < 0.5
-        assert_parity(ccl, img, conn, f"group seam trial {trial}")
+        tiled_parity(ccl, img, conn, rows, f"group seam trial {trial}")
 
 
+@pytest.mark.parametrize("rows", [32, 64, 128])
 @pytest.mark.parametrize("conn", [4, 8])
 @pytest.mark.parametrize("H,W", [(1000, 1000), (257, 1030), (1030, 257), (64 * 9, 64 * 9),
                                  (64 * 8 + 1, 64 * 8 - 1)])
-def test_multi_group_random(ccl, H, W, conn):
+def test_multi_group_random(ccl, H, W, conn, rows):
     for p in (0.45, 0.6):
-        assert_parity(ccl, wl.bernoulli(H, W, p, seed=H + 7 * W), conn, f"bernoulli{p}")
+        tiled_parity(ccl, wl.bernoulli(H, W, p, seed=H + 7 * W), conn, rows, f"bernoulli{p}")
 
 
 @pytest.mark.parametrize("conn", [4, 8])
@@ -326,10 +336,10 @@ def test_batch_c4_shapes(ccl, conn):
 
 
 def test_launch_policies_same_labels(ccl):
-    """Every launch shape of the local step and the final relabel (persistent
-    or one workgroup per tile) gives the oracle's labels, for single images
-    and batches across tile-count buckets; the tuner's choices are restored
-    afterwards."""
+    """Every tile height and every launch grid of the local step and the
+    final relabel (persistent or one workgroup per tile), set through the
+    launch policy, gives the oracle's labels, for single images and batches
+    across pixel buckets; the packaged choices are restored afterwards."""
     bounds = ccl.launch_buckets()
     singles = [wl.bernoulli(700, 900, 0.55, seed=21), wl.bernoulli(4096, 4096, 0.5, seed=22),
                wl.blobs(5000, 3000, 4, seed=23)]
@@ -340,41 +350,77 @@ def test_launch_policies_same_labels(ccl):
     dsingles = [to_dev(im) for im in singles]
     dbatch = [to_dev(im) for im in batch]
     try:
-        for local in (0, 1):
-            for final in (0, 1):
-                for cls in (0, 1):
-                    for b in range(len(bounds)):
-                        ccl.set_launch_policy(cls, b, local, final)
-                for c in (4, 8):
-                    for d, w in zip(dsingles, want_s[c]):
-                        out = ccl.label(d, c)
-                        torch.cuda.synchronize()
-                        assert np.array_equal(out.cpu().numpy(), w), (local, final, c)
-                outs = ccl.label_batch(dbatch, 8)
-                torch.cuda.synchronize()
-                for o, w in zip(outs, want_b):
-                    assert np.array_equal(o.cpu().numpy(), w), (local, final, "batch")
+        for rows in ccl.tile_shapes():
+            for local in (0, 1):
+                for final in (0, 1):
+                    for cls in (0, 1):
+                        for b in range(len(bounds)):
+                            for c in (4, 8):
+                                ccl.set_launch_policy(cls, b, c, rows, local, final)
+                    print(f"[parity] policy rows={rows} local={local} final={final}", flush=True)
+                    for c in (4, 8):
+                        for d, w in zip(dsingles, want_s[c]):
+                            out = ccl.label(d, c)
+                            torch.cuda.synchronize()
+                            assert np.array_equal(out.cpu().numpy(), w), (rows, local, final, c)
+                    outs = ccl.label_batch(dbatch, 8)
+                    torch.cuda.synchronize()
+                    for o, w in zip(outs, want_b):
+                        assert np.array_equal(o.cpu().numpy(), w), (rows, local, final, "batch")
     finally:
-        for cls in (0, 1):
-            for b in range(len(bounds)):
-                ccl.set_launch_policy(cls, b, -1, -1)
+        ccl.reset_launch_policy()
         if ccl.launch_policy_applied:
             ccl.apply_launch_policy(ccl.launch_policy_applied)
 
 
+@pytest.mark.parametrize("rows", [32, 64, 128])
+@pytest.mark.parametrize("conn", [4, 8])
+def test_tile_shape_independence(ccl, rows, conn):
+    """The same images give the same labels under every tile height (the
+    paper's block shape, Section 4.1), equal to the oracle's: the 512^2
+    Bernoulli(0.5) image, every 2048^2 content of the single-image sweep,
+    ragged and pitched sizes, and a batch of mixed sizes."""
+    cases = [wl.bernoulli(512, 512, 0.5, seed=s) for s in range(2)]
+    cases += [wl.make(kind, 2048, 2048, seed=0, **kw) for kind, kw in wl.single_image_contents()]
+    cases += [wl.bernoulli(H, W, p, seed=H + W) for H, W, p in
+              ((1, 1, 1.0), (1, 5000, 0.7), (5000, 1, 0.7), (33, 65, 0.5), (127, 129, 0.6),
+               (129, 63, 0.4), (257, 1000, 0.5), (1080, 1920, 0.45))]
+    for img in cases:
+        want = oracle_label(img, conn)
+        got = ccl.label(to_dev(img), conn, tile_rows=rows)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), (rows, conn, img.shape)
+    # a pitched view (row stride above the width)
+    big = wl.bernoulli(300, 700, 0.5, seed=9)
+    view = to_dev(big)[:, 3:650]
+    got = ccl.label(view, conn, tile_rows=rows)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle_label(np.ascontiguousarray(big[:, 3:650]),
+                                                           conn))
+    specs = wl.batch_specs(64, seed=40 + rows, lo=16, hi=1200)
+    imgs = [wl.make(k, H, W, seed=s, **kw) for (H, W, k, kw, s) in specs]
+    outs = ccl.label_batch([to_dev(im) for im in imgs], conn, tile_rows=rows)
+    torch.cuda.synchronize()
+    for im, o in zip(imgs, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle_label(im, conn)), (rows, conn, im.shape)
+    print(f"[parity] tile rows {rows} conn={conn}: {len(cases) + 1} images and a batch of "
+          f"{len(imgs)} exact", flush=True)
+
+
 def test_tuner_small_buckets(ccl, tmp_path):
-    """The tuner on the two smallest buckets: one choice per launch class and
-    bucket (an explicit one only where it beat the built-in rule), and labels
-    stay exact with the choices applied."""
+    """The tuner on the smallest bucket: one choice per launch class and
+    connectivity (an explicit one only where it beat the built-in choice),
+    and labels stay exact with the choices applied."""
     from paper_1712_09789_amd import tune
     try:
-        res = tune.tune(reps=2, buckets=[0, 1])
+        res = tune.tune(reps=2, buckets=[0])
         assert res["arch"].startswith("gfx")
         assert len(res["choices"]) == 4
         for ch in res["choices"]:
-            assert set(ch["us"]) == {"builtin", "0,0", "0,1", "1,0", "1,1"}
-            if ch["local"] >= 0:  # an explicit choice beat the built-in rule
-                t = ch["us"][f"{ch['local']},{ch['final']}"]
+            assert {f"r{r},-1,-1" for r in ccl.tile_shapes()} <= set(ch["us"])
+            assert "builtin" in ch["us"]
+            if ch["tile_rows"] or ch["local"] >= 0:  # an explicit choice beat the built-in one
+                t = ch["us"][f"r{ch['tile_rows']},{ch['local']},{ch['final']}"]
                 assert t == min(ch["us"].values()) and t < ch["us"]["builtin"]
         path = tmp_path / "policy.json"
         path.write_text(json.dumps(res))
@@ -382,9 +428,7 @@ def test_tuner_small_buckets(ccl, tmp_path):
         img = wl.bernoulli(1500, 1300, 0.5, seed=31)
         assert np.array_equal(gpu_label(ccl, img, 8), oracle_label(img, 8))
     finally:
-        for cls in (0, 1):
-            for b in range(len(ccl.launch_buckets())):
-                ccl.set_launch_policy(cls, b, -1, -1)
+        ccl.reset_launch_policy()
         if ccl.launch_policy_applied:
             ccl.apply_launch_policy(ccl.launch_policy_applied)
 

@@ -53,21 +53,24 @@ def test_table_special_patterns():
     assert all(int(r8[cb][k]) == 0 for k in fgc)
 
 
+@pytest.mark.parametrize("rows", [32, 64, 128])
 @pytest.mark.parametrize("conn", [4, 8])
-def test_seam_layout_assembly(conn):
+def test_seam_layout_assembly(conn, rows):
     """The exhaustive seam test's image assembly (run here on the CPU at a
-    smaller size): the oracle's labels of each assembled image equal the
-    expected map built from the pattern table, and the sites never touch."""
+    smaller size), for every tile height (merge groups of 256 x 256 pixels):
+    the oracle's labels of each assembled image equal the expected map built
+    from the pattern table, and the sites never touch."""
     import torch
     from oracle import oracle_label
     from seam_atlas import Layout
-    L = Layout(512, 704, 64, 64, 4, conn, "cpu")
+    gy = 256 // rows
+    L = Layout(512 + 2 * rows, 704, rows, 64, (gy, 4), conn, "cpu")
     cells = L.pos.reshape(-1)
     assert cells.unique().numel() == cells.numel()
     for n in (0, 1, 7):
         L.assemble(n)
-        img = L.img.view(512, 704).numpy()
-        want = L.want.view(512, 704).numpy()
+        img = L.img.view(L.H, 704).numpy()
+        want = L.want.view(L.H, 704).numpy()
         assert np.array_equal(oracle_label(img, conn), want), (n, conn)
     assert set(k[0] for k in L.keys) == {"corner", "vseam", "hseam"}
-    assert len(L.keys) == 16 + 4 + 4
+    assert len(L.keys) == gy * 4 + 4 + gy
