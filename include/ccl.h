@@ -78,6 +78,26 @@ int ccl_label(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
 int ccl_label_tiled(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
                     int32_t connectivity, int32_t* labels, int32_t tile_rows, void* stream);
 
+/*
+ * ccl_label for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same labels, computed with no hipMalloc, hipFree or other allocating call.
+ * The workspace is a fixed 32 MiB device array inside the library, one per
+ * device, held from the time the library's code is loaded on that device
+ * until the process ends; it fits images of up to about 4300 tiles of 64 x
+ * 64 pixels (4096 x 4096 fits).  The built-in tile shape and launch grids are
+ * used (the launch policy does not apply).  Every call on a device shares
+ * that device's array, so calls that overlap on one device (on different
+ * streams, or from several threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are ordered by the stream.
+ * Arguments and errors as ccl_label; CCL_ERR_TOO_LARGE also when the image
+ * needs more workspace than the array holds (checked before anything is
+ * enqueued).  The first call on a device looks up the array's device
+ * address (hipGetSymbolAddress); CCL_ERR_HIP if that fails.
+ */
+int ccl_label_noalloc(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                      int32_t connectivity, int32_t* labels, void* stream);
+
 /* One image of a batch; same meaning as the ccl_label arguments. */
 typedef struct {
     const uint8_t* img;

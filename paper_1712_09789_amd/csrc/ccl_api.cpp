@@ -446,6 +446,45 @@ static int label_one(const uint8_t* img, int32_t H, int32_t W, int64_t pitch, in
 // The built-in tile shape and grids (statistics, ablation, volumes, local step).
 static Choice builtin_choice() { return Choice{&r64::ops, GridChoice{}}; }
 
+// ---------------------------------------------------------------------------
+// fixed device scratch of ccl_label_noalloc
+// ---------------------------------------------------------------------------
+//
+// The workspace of ccl_label_noalloc lives in this file-scope device array,
+// which every device holds from the time the library's code is loaded on it
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// ever passed to kernels.  Nothing in the workspace needs to start at zero:
+// the local step writes every entry the later kernels read.
+
+constexpr int64_t NOALLOC_SCRATCH_BYTES = int64_t(32) << 20;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;  // device -> address of its copy of scratch
+
+static int scratch_address(void** out, const char* who)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: hipGetDevice: %s", who, hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    const auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return CCL_OK;
+    }
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(CCL_ERR_HIP, "%s: hipGetSymbolAddress(scratch) on device %d: %s", who, dev,
+                    hipGetErrorString(e));
+    g_scratch_addr[dev] = ptr;
+    *out = ptr;
+    return CCL_OK;
+}
+
 // Labels a batch: one set of launches per connectivity class, each with the
 // tile shape the policy (or `forced_rows`) picks for it.
 static int label_batch(const ccl_image_desc* descs, int32_t n, int forced_rows, hipStream_t st,
@@ -524,6 +563,45 @@ int ccl_label(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
     const Choice ch = choose(false, (int64_t)H * W, connectivity, 0);
     return label_one(img, H, W, pitch_bytes, connectivity, labels,
                      static_cast<hipStream_t>(stream), false, ch, "ccl_label");
+}
+
+int ccl_label_noalloc(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,
+                      int32_t connectivity, int32_t* labels, void* stream)
+{
+    g_err.clear();
+    const char* who = "ccl_label_noalloc";
+    int rc = validate(img, H, W, pitch_bytes, connectivity, labels, who);
+    if (rc != CCL_OK || H == 0 || W == 0) return rc;
+    // the built-in tile shape and grids: the scratch is sized for them
+    const Choice ch = builtin_choice();
+    const int64_t ntiles = tiles_of(H, W, ch.ops->rows);
+    const int64_t need = node_ids_fit(ntiles, ch.ops->rows)
+                             ? workspace_bytes(ntiles, ch.ops->rows)
+                             : INT64_MAX;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(CCL_ERR_TOO_LARGE, "%s: %dx%d needs %lld workspace bytes; the fixed scratch "
+                    "holds %lld (about %lld tiles of %dx%d pixels)", who, H, W,
+                    (long long)(need == INT64_MAX ? -1 : need), (long long)NOALLOC_SCRATCH_BYTES,
+                    (long long)(NOALLOC_SCRATCH_BYTES /
+                                (ch.ops->rows * 8 + nslots(ch.ops->rows) * 12 +
+                                 runtab_per_tile(ch.ops->rows) * 2 + 4)),
+                    ch.ops->rows, TW);
+    void* base = nullptr;
+    rc = scratch_address(&base, who);
+    if (rc != CCL_OK) return rc;
+    std::vector<ImageArgs> one(1, make_args(img, H, W, pitch_bytes, labels, ch.ops->rows));
+    ClassLayout L;
+    rc = layout_class(one, connectivity, *ch.ops, L, who);
+    if (rc != CCL_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchArgs b;
+    Workspace ws;
+    // a single image: no device tables, so nothing is copied
+    rc = bind_class(one, L, base, false, st, b, ws, who);
+    if (rc != CCL_OK) return rc;
+    hipError_t e = ch.ops->label(b, connectivity, ws, st, nullptr, false, ch.grid, nullptr);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return CCL_OK;
 }
 
 int ccl_label_tiled(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_bytes,

@@ -49,7 +49,7 @@ FAKE_IMG = 0x10000000
 FAKE_OUT = 0x20000000
 
 
-@pytest.mark.parametrize("name", ["ccl_label", "ccl_label_local"])
+@pytest.mark.parametrize("name", ["ccl_label", "ccl_label_local", "ccl_label_noalloc"])
 @pytest.mark.parametrize("args,status", [
     ((FAKE_IMG, -1, 4, 4, 8, FAKE_OUT), -1),       # negative height
     ((FAKE_IMG, 4, -4, 4, 8, FAKE_OUT), -1),       # negative width
@@ -175,6 +175,15 @@ def test_tiled_entry_points_validate(lib):
         # one pixel row per tile row of a 2^31-wide image: too many tiles
         assert L.ccl_label_tiled(FAKE_IMG, 1, (1 << 31) - 1, (1 << 31) - 1, 8,
                                  FAKE_OUT + (1 << 33), rows, None) == -2
+
+
+def test_noalloc_size_limit(lib):
+    """Images whose workspace exceeds the fixed scratch are rejected on the
+    host, before any device call; the 4096^2 headline size fits."""
+    f = _label(lib, "ccl_label_noalloc")
+    assert f(FAKE_IMG, 8192, 8192, 8192, 8, FAKE_OUT + (1 << 30), None) == -2
+    assert b"fixed scratch" in lib.ccl_last_error()
+    assert f(FAKE_IMG, 1, (1 << 31) - 1, (1 << 31) - 1, 8, FAKE_OUT + (1 << 33), None) == -2
 
 
 def test_copy_validation(lib):
