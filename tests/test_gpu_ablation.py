@@ -112,3 +112,48 @@ def test_counters_closed_forms(ccl):
     assert (cc[:, 1] >= 63).all()        # 64 column chains joined by unions
     _, n = run(ccl, full, "NC2FL")
     assert (n[:, 1] >= 4095).all()       # 4096 pixels joined by unions
+
+
+def mean_atomics(ccl, img, variant):
+    return float(run(ccl, img, variant)[1][:, 1].mean())
+
+
+def test_c2fl_fewest_atomics_every_size_and_density(ccl):
+    """Section 4.1 (effectiveness of coarse labelling): the method (C2FL)
+    takes the fewest atomic operations of the four variants, at every image
+    size of its sweep (Bernoulli 0.5, 64^2 .. 2048^2) and every foreground
+    density 0.1 .. 0.9 (2048^2)."""
+    cases = [(f"{n}^2 p=0.5", wl.bernoulli(n, n, 0.5, seed=n)) for n in (64, 128, 256, 512,
+                                                                         1024, 2048)]
+    cases += [(f"2048^2 p={p10 / 10}", wl.bernoulli(2048, 2048, p10 / 10, seed=p10))
+              for p10 in range(1, 10)]
+    for what, img in cases:
+        at = {v: mean_atomics(ccl, img, v) for v in VARIANTS}
+        print(f"[ablation] {what}: mean atomics per tile {at}", flush=True)
+        assert at["C2FL"] < min(at[v] for v in VARIANTS if v != "C2FL"), (what, at)
+
+
+def test_atomics_per_tile_independent_of_size(ccl):
+    """Section 4.1: the atomic operations per block do not grow with the
+    image (Bernoulli 0.5; whole 64 x 64 tiles from 128^2 up): every
+    variant's mean per tile stays within 10 % across 128^2 .. 2048^2."""
+    for v in VARIANTS:
+        means = [mean_atomics(ccl, wl.bernoulli(n, n, 0.5, seed=n), v)
+                 for n in (128, 256, 512, 1024, 2048)]
+        print(f"[ablation] {v}: mean atomics per tile by size {means}", flush=True)
+        assert max(means) <= 1.10 * min(means), (v, means)
+
+
+def test_mid_densities_are_the_worst_case(ccl):
+    """Section 4.1: the work peaks at middle densities.  For every variant
+    the mean atomics per tile rise from density 0.1 through 0.5, and the
+    largest count lies strictly inside (0.1, 0.9)."""
+    dens = [p10 / 10 for p10 in range(1, 10)]
+    imgs = [wl.bernoulli(1024, 1024, p, seed=int(10 * p)) for p in dens]
+    for v in VARIANTS:
+        at = [mean_atomics(ccl, im, v) for im in imgs]
+        print(f"[ablation] {v}: mean atomics per tile by density {at}", flush=True)
+        assert at[0] < at[2] < at[4], (v, at)
+        peak = dens[int(np.argmax(at))]
+        if v in ("C2FL", "RC2FL"):
+            assert 0.1 < peak < 0.9, (v, at)
