@@ -792,10 +792,14 @@ def main():
             d = [(torch.from_numpy(img).to(dev),
                   torch.empty((big, big), dtype=torch.int32, device=dev), 8)]
             s, _ = time_rotation(ccl, torch, d, 20, 3)
+            # per-kernel averages from a second region with events around every kernel
+            _, kern = time_rotation(ccl, torch, d, 10, 1, timing=list(KERNEL_NAMES))
             gpx = 20 * big * big / s / 1e9
             extra[f"{kind}{kw}"] = {"Gpx/s": round(gpx, 1),
                                     "us": round(1e6 * s / 20, 1),
-                                    "path_hbm_frac": round(PATH_BYTES_PER_PX * gpx / HBM_PEAK_GBS, 4)}
+                                    "path_hbm_frac": round(PATH_BYTES_PER_PX * gpx / HBM_PEAK_GBS, 4),
+                                    "kernel_avg_us": {k: round(1e3 * v[0] / v[1], 1)
+                                                      for k, v in kern.items() if v[1]}}
             del d
             torch.cuda.empty_cache()
         result["extra_8192_conn8"] = extra

@@ -448,9 +448,31 @@ __device__ __forceinline__ V ld_uniform(const V* p)
 #endif
 }
 
+// The fields are read one by one: a whole-struct copy is lowered to vector
+// loads, whose wait would also wait for every store issued before them.
 __device__ __forceinline__ ImageArgs batch_image(const BatchArgs& b, int i)
 {
-    return b.n == 1 ? b.one : ld_uniform(b.imgs + i);
+    if (b.n == 1) return b.one;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __attribute__((address_space(4))) ImageArgs* p =
+        (const __attribute__((address_space(4))) ImageArgs*)(b.imgs + i);
+#else
+    const ImageArgs* p = b.imgs + i;  // host pass: never executed
+#endif
+    ImageArgs r;
+    r.img = p->img;
+    r.pitch = p->pitch;
+    r.labels = p->labels;
+    r.H = p->H;
+    r.W = p->W;
+    r.ntx = p->ntx;
+    r.nty = p->nty;
+    r.wmagic = p->wmagic;
+    r.lbase = p->lbase;
+    r.unused = 0;
+    r.vec_out = p->vec_out;
+    r.tbase = p->tbase;
+    return r;
 }
 __device__ __forceinline__ int tile_image(const BatchArgs& b, int64_t T)
 {
