@@ -141,6 +141,8 @@ struct StatsWs {
     uint32_t* boff;      // [nblk] exclusive scan of bsum
     StatRec* rec0;       // [ntiles][nslots] per tile: partials of its border components
     uint32_t* cnt0;      // [ntiles]
+    int32_t* fin;        // [ntiles][nslots] final label of the component at each
+                         // foreground border slot
     int64_t nseg, nblk;
     int32_t g1x, g1y;    // grid of merge workgroups (4 x 4 tiles each)
     CompStats* comps;    // caller's output [capacity]
@@ -153,7 +155,8 @@ inline int64_t stats_workspace_bytes(int64_t ntiles)
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     const int64_t nseg = ntiles * DEFAULT_ROWS, nblk = (nseg + SCAN_BLK - 1) / SCAN_BLK;
     return up(nseg * 8) + up(nseg * 4) + 2 * up(nblk * 4) +
-           up(ntiles * nslots(DEFAULT_ROWS) * (int64_t)sizeof(StatRec)) + up(ntiles * 4);
+           up(ntiles * nslots(DEFAULT_ROWS) * (int64_t)sizeof(StatRec)) + up(ntiles * 4) +
+           up(ntiles * nslots(DEFAULT_ROWS) * 4);
 }
 
 inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
@@ -176,6 +179,8 @@ inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
     s.rec0 = reinterpret_cast<StatRec*>(p);
     p += up(ntiles * nslots(DEFAULT_ROWS) * (int64_t)sizeof(StatRec));
     s.cnt0 = reinterpret_cast<uint32_t*>(p);
+    p += up(ntiles * 4);
+    s.fin = reinterpret_cast<int32_t*>(p);
     return s;
 }
 

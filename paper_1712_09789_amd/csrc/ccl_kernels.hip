@@ -1180,6 +1180,11 @@ __device__ void final_tile(const BatchArgs& b, const Workspace& ws, const StatsW
             }
         }
         sh.fin[tid + k * NT] = (int32_t)((uint32_t)(vk >> 32) + 1u) + a.lbase;
+        // with statistics, every foreground border slot publishes its
+        // component's label; the statistics pass reads it at the component's
+        // representative slot (the slot itself may name another node: the
+        // block merge rewrites outer slots to group roots)
+        if (STATS) st.fin[T * NSLOTS + tid + k * NT] = sh.fin[tid + k * NT];
     }
     __syncthreads();
     for (uint32_t id = tid; id < R; id += NT) {
@@ -1374,6 +1379,10 @@ struct StatsShared : Lines<D> {
     // interior components, at the run holding their smallest pixel
     uint64_t isums[Geo<D>::MAXR], icols[Geo<D>::MAXR], irows[Geo<D>::MAXR];
     uint8_t iroot[Geo<D>::MAXR];
+    // this tile's rows: number of the first component whose smallest pixel
+    // lies in the row segment, and those smallest pixels
+    uint32_t segnum[TILE_ROWS];
+    uint64_t rootb[TILE_ROWS];
     uint32_t nrec;
 };
 
@@ -1402,17 +1411,29 @@ __device__ __forceinline__ int64_t component_number(const ImageArgs& a, const St
            popc64(st.rootbits[rt] & ((1ull << (rx % TW)) - 1ull));
 }
 
-// Statistics of every run of a tile.  A run's label is read back from the
-// label map at its smallest pixel.  Runs of interior components (wholly in
-// this tile) are summed in LDS at the run holding the component's smallest
-// pixel, which then writes the whole entry; runs of border components are
-// summed per component in LDS and leave the tile as one partial record each,
-// which k_stats_merge combines over 4 x 4 tiles before they reach the
-// entries, so that a component spanning the image is not updated once per
-// tile.  The run holding a border component's smallest pixel writes the
-// entry's starting values (label, top row, empty sums and box).
-constexpr int ST = 1024;  // k_stats threads per tile: latency of the per-run loads is hidden
-                          // inside the workgroup (its LDS allows two per compute unit)
+// Number of a component whose smallest pixel is at tile position (ky, kx)
+// of the tile in sh (its rows' scanned counts and smallest pixels staged).
+template <typename SH>
+__device__ __forceinline__ int64_t tile_number(const SH& sh, int ky, int kx)
+{
+    return (int64_t)sh.segnum[ky] + popc64(sh.rootb[ky] & ((1ull << kx) - 1ull));
+}
+
+// Statistics of every run of a tile.  A run's label is its border
+// component's final label (published by the relabel at the component's
+// representative slot) or its interior component's root position, so no
+// label is read back from the label map.  Runs of interior components
+// (wholly in this tile) are summed in LDS at the run holding the component's
+// smallest pixel, which then writes the whole entry; runs of border
+// components are summed per component in LDS and leave the tile as one
+// partial record each, which k_stats_merge combines over 4 x 4 tiles before
+// they reach the entries, so that a component spanning the image is not
+// updated once per tile.  The run holding a border component's smallest
+// pixel writes the entry's starting values (label, top row, empty sums and
+// box).  Components whose smallest pixel lies in this tile are numbered
+// from the tile's staged row counts.
+constexpr int ST = 1024;  // k_stats threads per tile (its LDS allows two workgroups per
+                          // compute unit, so a wide workgroup keeps the unit busy)
 template <int D>
 __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs st)
 {
@@ -1424,9 +1445,15 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int gx0 = tx * TW, gy0 = ty * TILE_ROWS;
 
-    if (tid < TILE_ROWS) sh.M[tid] = ws.bits[T * TILE_ROWS + tid];
+    if (tid < TILE_ROWS) {
+        sh.M[tid] = ws.bits[T * TILE_ROWS + tid];
+        sh.rootb[tid] = st.rootbits[T * TILE_ROWS + tid];
+        const int64_t sg = (int64_t)(gy0 + tid) * a.ntx + tx;
+        sh.segnum[tid] = gy0 + tid < a.H ? st.seg[sg] + st.boff[sg / SCAN_BLK] : 0u;
+    }
     if (tid < NSLOTS) {
         sh.sums[tid] = sh.cols[tid] = sh.rows[tid] = 0ull;
+        sh.lab[tid] = st.fin[T * NSLOTS + tid];  // used at representative slots only
     }
     if (tid == 0) sh.nrec = 0u;
     __syncthreads();
@@ -1467,7 +1494,13 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         const uint64_t colm = span_mask(s0, e);
         const uint64_t packed = (uint64_t)area | ((uint64_t)sx << 13) | ((uint64_t)sy << 31);
         const int64_t kpos = (int64_t)(gy0 + (int)(key / TW)) * a.W + gx0 + (int)(key % TW);
-        const int32_t L = ld_global(a.labels + kpos);
+        // the run's label: a border component's from the relabel (at its
+        // representative slot), an interior one's from its root's tile key
+        const uint32_t en = sh.ent[id];
+        const bool border = (en & RT_BORDER) != 0;
+        const int32_t L = border ? sh.lab[en & 0x7fff]
+                                 : (int32_t)((int64_t)(gy0 + (int)(en / TW)) * a.W + gx0 +
+                                             (int)(en % TW) + 1);
         if (L <= 0 || (int64_t)L > kpos + 1) {
             // a foreground pixel's label is 1 + a position at or before it;
             // anything else means the labels are wrong: poison the count so
@@ -1476,8 +1509,6 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
             continue;
         }
         const bool is_root = kpos == (int64_t)L - 1;
-        const uint32_t en = sh.ent[id];
-        const bool border = (en & RT_BORDER) != 0;
         if (!border) {
             // the run holding the smallest pixel (tile position = the entry)
             const int ky = (int)(en / TW), kx = (int)(en % TW);
@@ -1494,12 +1525,11 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
             atomicAdd(&sh.sums[rep], packed);
             atomicOr(&sh.cols[rep], colm);
             atomicOr(&sh.rows[rep], rowm);
-            sh.lab[rep] = L;
-            if (!is_root) continue;  // only the label remains to write
+            if (!is_root) continue;
         }
         // the component's entry starts from its label and top row; the
         // merge adds every tile's part to it
-        const int64_t num = component_number(a, st, L);
+        const int64_t num = tile_number(sh, (int)(key / TW), (int)(key % TW));
         if (num >= st.capacity) continue;
         CompStats c;
         c.label = L;
@@ -1526,7 +1556,7 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         }
         const int64_t kpos = (int64_t)(gy0 + ky) * a.W + gx0 + kx;
         const int32_t L = (int32_t)(kpos + 1);
-        const int64_t num = component_number(a, st, L);
+        const int64_t num = tile_number(sh, ky, kx);
         if (num >= st.capacity) continue;
         const uint64_t v = sh.isums[id], cm = sh.icols[id], rm = sh.irows[id];
         const int area = (int)(v & 0x1fffu);
