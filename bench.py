@@ -123,8 +123,11 @@ def load_traffic(src_hash, kernel):
 
 def _short_kernel(name):
     import re
-    m = re.search(r"ccl::(k_\w+)(<[^>(]*>)?", name)
-    return (m.group(1) + (m.group(2) or "")) if m else name[:48]
+    m = re.search(r"ccl::(?:(r\d+)::)?(k_\w+)(<[^>(]*>)?", name)
+    if not m:
+        return name[:48]
+    shape = f" ({m.group(1)})" if m.group(1) else ""  # tile-height build of the kernel
+    return m.group(2) + (m.group(3) or "") + shape
 
 
 def summarize_trace(db, out, cmd):
@@ -158,7 +161,7 @@ def summarize_counters(db, out, cmd, px=4096 * 4096):
     for name, counter, _, v in rows:
         agg[(_short_kernel(name), counter)].append(v)
     counters = sorted({c for _, c in agg})
-    kernels = sorted({k for k, _ in agg if k.startswith("k_") and k != "k_copy"})
+    kernels = sorted({k for k, _ in agg if k.startswith("k_") and not k.startswith("k_copy")})
     lines = ["# Counters per launch: " + os.path.basename(out).rsplit(".", 1)[0], "",
              "Produced by:", "", "```", cmd, "```", "",
              f"kernel_source_hash: {kernel_source_hash()}", "",
@@ -186,36 +189,78 @@ def _counter_mean(db, kernel_sub, counter):
     return sum(vals) / len(vals), len(vals)
 
 
-def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes, out, cmd,
-                      px=4096 * 4096):
+# Read request size of each kernel's bulk reads, for the FETCH_SIZE factor:
+# k_local reads each tile row's 64 bytes as one request; the others read
+# whole contiguous blocks (slots, forest entries, bitmasks, run tables).
+KERNEL_READ_REQUEST = {"local": 64, "block": 128, "seam": 128, "final": 128}
+
+
+def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes,
+                      seg_fetch_db, seg_bytes, out, cmd, px=4096 * 4096):
     """FETCH_SIZE / WRITE_SIZE runs of the labelling kernels, scaled by what the
-    same counters read for the copy kernel over a known number of bytes."""
+    same counters read for a copy of a known number of bytes: the contiguous
+    copy kernel (128-byte requests) and the gathering copy of 64-byte
+    segments; each kernel's reads take the factor of its request size."""
     cf_kib, _ = _counter_mean(copy_fetch_db, "k_copy", "FETCH_SIZE")
     cw_kib, _ = _counter_mean(copy_write_db, "k_copy", "WRITE_SIZE")
+    sf_kib, _ = _counter_mean(seg_fetch_db, "k_copy_seg", "FETCH_SIZE")
     ff = copy_bytes / (cf_kib * 1024.0)
     wf = copy_bytes / (cw_kib * 1024.0)
+    sf = seg_bytes / (sf_kib * 1024.0)
+    read_factor = {128: ff, 64: sf}
     lines = ["# HBM traffic per launch on the 4096x4096 headline workload", "",
              "Produced by (each counter in its own run):", "", "```", cmd, "```", "",
              f"kernel_source_hash: {kernel_source_hash()}",
              f"copy_bytes: {copy_bytes}",
              f"copy_fetch_kib: {cf_kib:.1f}",
              f"copy_write_kib: {cw_kib:.1f}",
+             f"segment_copy_bytes: {seg_bytes}",
+             f"segment_copy_fetch_kib: {sf_kib:.1f}",
              f"fetch_factor: {ff:.4f}",
+             f"fetch_factor_64B_requests: {sf:.4f}",
              f"write_factor: {wf:.4f}", "",
-             "| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes | algorithmic bytes |",
-             "|---|---|---|---|---|---|"]
+             "| kernel | launches | FETCH_SIZE KiB | read request | WRITE_SIZE KiB | scaled bytes | "
+             "algorithmic bytes |",
+             "|---|---|---|---|---|---|---|"]
     fields = []
+    path_total = 0.0
     for kind, kname in KERNEL_NAMES.items():
         f_kib, nf = _counter_mean(fetch_db, kname, "FETCH_SIZE")
         w_kib, nw = _counter_mean(write_db, kname, "WRITE_SIZE")
-        total = f_kib * 1024.0 * ff + w_kib * 1024.0 * wf
+        req = KERNEL_READ_REQUEST[kind]
+        total = f_kib * 1024.0 * read_factor[req] + w_kib * 1024.0 * wf
+        path_total += total
         algo = KERNEL_BYTES_PER_PX.get(kind, 0.0) * px
-        lines.append(f"| {kname} | {nf} | {f_kib:.1f} | {w_kib:.1f} | {total:.0f} | "
+        lines.append(f"| {kname} | {nf} | {f_kib:.1f} | {req} B | {w_kib:.1f} | {total:.0f} | "
                      f"{algo:.0f} |")
         fields.append(f"{kind}_bytes_per_launch: {total:.0f}")
+    fields.append(f"path_bytes_per_px: {path_total / px:.3f}")
     lines += [""] + fields + [""]
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+
+def replay_durations(ccl, torch, devs, reps=10):
+    """Average duration (microseconds) of one launch of k_local and of
+    k_final over the rotation: each image is labelled, one of its kernels
+    is launched `reps` more times back to back between two events
+    (ccl_replay_last, on the current stream), and the image is labelled
+    again (replaying the local step resets the merge state)."""
+    st = torch.cuda.current_stream()
+    out_us = {}
+    for kind in ("local", "final"):
+        tot = 0.0
+        for img, out, conn in devs:
+            ccl.label(img, conn, out=out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            ccl.replay_last(kind, reps)
+            e1.record(st)
+            ccl.label(img, conn, out=out)
+            torch.cuda.synchronize()
+            tot += 1e3 * e0.elapsed_time(e1) / reps
+        out_us[kind] = round(tot / len(devs), 2)
+    return out_us
 
 
 def step_distribution(ccl, torch, devs, steps):
@@ -592,14 +637,17 @@ def main():
                          "connectivities, ROUNDS times (for a kernel trace) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel over MIB MiB (counter calibration)")
+    ap.add_argument("--calibrate-segments", type=int, default=0, metavar="MIB",
+                    help="only run the gathering copy of 64-byte segments (one every 256 "
+                         "bytes) into MIB MiB (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("DB", "OUT", "CMD"),
                     help="write a markdown table of a --pmc run's counters per kernel and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT", "CMD"),
                     help="write a rocprofv3 kernel-trace summary (no GPU needed)")
-    ap.add_argument("--summarize-traffic", nargs=7,
+    ap.add_argument("--summarize-traffic", nargs=9,
                     metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB",
-                             "COPY_BYTES", "OUT", "CMD"),
-                    help="write the k_final HBM traffic summary (no GPU needed)")
+                             "COPY_BYTES", "SEG_FETCH_DB", "SEG_BYTES", "OUT", "CMD"),
+                    help="write the per-kernel HBM traffic summary (no GPU needed)")
     args = ap.parse_args()
 
     if args.summarize_counters:
@@ -610,7 +658,7 @@ def main():
         return
     if args.summarize_traffic:
         a = args.summarize_traffic
-        summarize_traffic(a[0], a[1], a[2], a[3], int(a[4]), a[5], a[6])
+        summarize_traffic(a[0], a[1], a[2], a[3], int(a[4]), a[5], int(a[6]), a[7], a[8])
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -641,6 +689,23 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": n,
                           "avg_us": 1e3 * ms / n,
                           "read_plus_write_GBs": 2 * nbytes / (ms / n / 1e3) / 1e9}))
+        return
+
+    if args.calibrate_segments:
+        nbytes = args.calibrate_segments << 20
+        src = torch.ones(nbytes * 4, dtype=torch.uint8, device=dev)
+        dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            ccl.copy_segments(src, dst, 64, 256)
+        torch.cuda.synchronize()
+        ccl.timing_enable(True)
+        for _ in range(10):
+            ccl.copy_segments(src, dst, 64, 256)
+        k = ccl.timing_read()
+        ccl.timing_enable(False)
+        ms, n = k["copy"]
+        print(json.dumps({"segment_copy_bytes": nbytes, "launches": n,
+                          "avg_us": 1e3 * ms / n}))
         return
 
     if args.profile_volume:
@@ -706,14 +771,14 @@ def main():
                "host": host_cpu()}
 
     # timed region (headline value); then a region with events around every
-    # kernel (per-kernel breakdown) and one with events around the dominant
-    # kernel only (its duration, for the roofline figure)
+    # kernel (per-kernel breakdown), and back-to-back launches of k_local and
+    # of k_final alone (their launch durations, for the roofline figure)
     secs, _ = time_rotation(ccl, torch, devs, args.steps, args.warmup)
     secs_all, kern = time_rotation(ccl, torch, devs, args.steps, args.warmup,
                                    timing=["local", "block", "seam", "final"])
     kavg = {k: round(1e3 * v[0] / v[1], 2) for k, v in kern.items() if v[1]}
-    dom = max(("local", "final"), key=lambda k: kavg.get(k, 0.0))
-    _, kdom = time_rotation(ccl, torch, devs, args.steps, args.warmup, timing=[dom])
+    replay_us = replay_durations(ccl, torch, devs)
+    dom = max(("local", "final"), key=lambda k: replay_us[k])
     dist = step_distribution(ccl, torch, devs, max(args.steps, 20))
     # (after the timed regions, and left out of profiled runs: concurrent
     # kernels would blur per-kernel durations)
@@ -726,9 +791,11 @@ def main():
         f"(events around every kernel: {1e6 * secs_all / args.steps:.1f} us/step); "
         f"kernel avg us {kavg}")
 
-    dom_ms, dom_n = kdom[dom]
-    dom_avg_s = dom_ms / dom_n / 1e3
-    algo_bytes = KERNEL_BYTES_PER_PX[dom] * px
+    # the roofline rule: the path's algorithmic bytes per pixel (5: 1 read,
+    # 4 written) times the pixels one launch processes, over the dominant
+    # kernel's launch duration
+    dom_avg_s = replay_us[dom] * 1e-6
+    algo_bytes = PATH_BYTES_PER_PX * px
     achieved = algo_bytes / dom_avg_s / 1e9
     src_hash = kernel_source_hash()
     traffic = load_traffic(src_hash, dom)
@@ -760,20 +827,26 @@ def main():
         "copy_GBs": round(copy_gbs, 1),
         "path_copy_frac": round(PATH_BYTES_PER_PX * value / copy_gbs, 4),
         "kernel_avg_us": kavg,
+        # one launch of k_local / k_final alone, back to back (ccl_replay_last)
+        "kernel_launch_us": {KERNEL_NAMES[k]: v for k, v in replay_us.items()},
         # launch-shape cache the binding applied (tune.py); None = built-in rule
         "launch_policy": (os.path.basename(ccl.launch_policy_applied)
                           if ccl.launch_policy_applied else None),
-        # every kernel with algorithmic bytes, against HBM peak (durations from
-        # the region with events around every kernel)
+        # every kernel with algorithmic bytes, on its own bytes (k_local:
+        # image read + bitmask write; k_final: label write + bitmask read),
+        # against HBM peak, over its back-to-back launch duration
         "kernel_hbm": {KERNEL_NAMES[k]: {
-            "GBs": round(KERNEL_BYTES_PER_PX[k] * px / (kavg[k] * 1e-6) / 1e9, 1),
-            "frac": round(KERNEL_BYTES_PER_PX[k] * px / (kavg[k] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
-            for k in KERNEL_BYTES_PER_PX if kavg.get(k)},
+            "bytes_per_px": KERNEL_BYTES_PER_PX[k],
+            "GBs": round(KERNEL_BYTES_PER_PX[k] * px / (replay_us[k] * 1e-6) / 1e9, 1),
+            "frac": round(KERNEL_BYTES_PER_PX[k] * px / (replay_us[k] * 1e-6) / 1e9 /
+                          HBM_PEAK_GBS, 4)}
+            for k in KERNEL_BYTES_PER_PX},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": algo_bytes,
+                     "algorithmic_bytes_per_px": PATH_BYTES_PER_PX,
                      "avg_launch_us": round(dom_avg_s * 1e6, 2),
                      # the whole path on the same basis: 5 B/px (1 B read, 4 B
                      # written) per step over the measured step time

@@ -313,11 +313,38 @@ int ccl_timing_enable(int32_t enable);
 int ccl_timing_read(double* ms, int64_t* launches, int32_t n);
 
 /*
+ * Benchmark hook: enqueue `reps` more launches of one kernel of the most
+ * recent plain labelling (ccl_label, ccl_label_tiled, ccl_label_batch,
+ * ccl_label_batch_tiled) made by the calling thread on the current device,
+ * back to back on `stream`, with that call's arguments, workspace and launch
+ * shape, so that a timer around the call measures that kernel alone.
+ *   kind  0 = the local step, 2 = the final relabel (the kinds of
+ *         ccl_timing_enable).
+ * The final relabel rewrites the same labels.  The local step resets the
+ * block merge's state in the workspace, so after it the labels of that call
+ * are valid only once it is made again.  The workspace must not have been
+ * used by a larger call on the same stream since.  CCL_ERR_INVALID_ARG for
+ * another kind, reps < 0, or no such call.
+ */
+int ccl_replay_last(int32_t kind, int32_t reps, void* stream);
+
+/*
  * Plain device-to-device copy of `bytes` bytes (both device pointers,
  * 16-byte aligned, non-overlapping) by a streaming kernel.  Used only to
  * calibrate bandwidth figures and hardware byte counters.
  */
 int ccl_copy_bytes(const void* src, void* dst, int64_t bytes, void* stream);
+
+/*
+ * Gathering copy for the same calibration, in the request size of the local
+ * step's image reads: `bytes` bytes go to dst (contiguous) from segments of
+ * `segment_bytes` taken one every `src_stride_bytes` bytes of src (src must
+ * hold bytes / segment_bytes such strides).  All sizes, the stride and both
+ * pointers 16-byte aligned, bytes a multiple of the segment, stride >=
+ * segment.
+ */
+int ccl_copy_segments(const void* src, void* dst, int64_t bytes, int32_t segment_bytes,
+                      int64_t src_stride_bytes, void* stream);
 
 #ifdef __cplusplus
 }

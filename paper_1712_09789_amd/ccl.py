@@ -79,6 +79,10 @@ def _load() -> ctypes.CDLL:
     lib.ccl_timing_read.restype = ctypes.c_int
     lib.ccl_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), i32]
+    lib.ccl_copy_segments.restype = ctypes.c_int
+    lib.ccl_copy_segments.argtypes = [vp, vp, i64, i32, i64, vp]
+    lib.ccl_replay_last.restype = ctypes.c_int
+    lib.ccl_replay_last.argtypes = [i32, i32, vp]
     lib.ccl_copy_bytes.restype = ctypes.c_int
     lib.ccl_copy_bytes.argtypes = [vp, vp, i64, vp]
     lib.ccl_plan_create.restype = ctypes.c_int
@@ -389,6 +393,23 @@ def timing_read() -> dict:
     if k < 0:
         _check(k)
     return {KERNEL_KINDS[i]: (float(ms[i]), int(n[i])) for i in range(nk)}
+
+
+def copy_segments(src: torch.Tensor, dst: torch.Tensor, segment_bytes: int,
+                  src_stride_bytes: int, stream=None) -> None:
+    """Gather dst.nbytes bytes from segments of src (ccl_copy_segments)."""
+    nbytes = dst.numel() * dst.element_size()
+    if (nbytes // segment_bytes) * src_stride_bytes > src.numel() * src.element_size():
+        raise ValueError("src is too small for the segments")
+    _check(_lib.ccl_copy_segments(src.data_ptr(), dst.data_ptr(), nbytes, int(segment_bytes),
+                                  int(src_stride_bytes), _stream_handle(stream)))
+
+
+def replay_last(kind: str, reps: int, stream=None) -> None:
+    """Launch one kernel ("local" or "final") of this thread's most recent
+    labelling call `reps` more times, back to back (ccl_replay_last; after
+    "local" the labels are valid again only once the call is repeated)."""
+    _check(_lib.ccl_replay_last(KERNEL_KINDS.index(kind), int(reps), _stream_handle(stream)))
 
 
 def copy_bytes(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

@@ -397,6 +397,17 @@ struct StatsOut {
 // the head of the workspace) that maps global tiles, merge groups and seam
 // workgroups back to their image.
 
+// The most recent plain labelling launched by this thread (for ccl_replay_last).
+struct LastLaunch {
+    bool valid = false;
+    int device = 0;
+    int conn = 0;
+    Choice ch{};
+    BatchArgs b{};
+    Workspace ws{};
+};
+static thread_local LastLaunch g_last;
+
 static int run_batch(std::vector<ImageArgs>& imgs, int conn, const Choice& ch, hipStream_t st,
                      bool local_only, const char* who, const StatsOut* so = nullptr,
                      int ablation = -1, uint32_t* counters = nullptr)
@@ -427,6 +438,13 @@ static int run_batch(std::vector<ImageArgs>& imgs, int conn, const Choice& ch, h
         e = ch.ops->label(b, conn, ws, st, active_timer(), local_only, ch.grid,
                           so ? &sw : nullptr);
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
+    if (!so && ablation < 0 && !local_only) {
+        g_last.valid = hipGetDevice(&g_last.device) == hipSuccess;
+        g_last.conn = conn;
+        g_last.ch = ch;
+        g_last.b = b;
+        g_last.ws = ws;
+    }
     return CCL_OK;
 }
 
@@ -978,6 +996,24 @@ int ccl_timing_read(double* ms, int64_t* launches, int32_t n)
     return NKINDS;
 }
 
+int ccl_replay_last(int32_t kind, int32_t reps, void* stream)
+{
+    g_err.clear();
+    const char* who = "ccl_replay_last";
+    if (kind != KIND_LOCAL && kind != KIND_FINAL)
+        return fail(CCL_ERR_INVALID_ARG, "%s: kind %d is not 0 (local step) or 2 (final relabel)",
+                    who, kind);
+    if (reps < 0) return fail(CCL_ERR_INVALID_ARG, "%s: reps = %d", who, reps);
+    int dev = -1;
+    if (!g_last.valid || hipGetDevice(&dev) != hipSuccess || dev != g_last.device)
+        return fail(CCL_ERR_INVALID_ARG, "%s: no labelling call on this thread and device", who);
+    hipError_t e = g_last.ch.ops->replay(g_last.b, g_last.conn, g_last.ws,
+                                         static_cast<hipStream_t>(stream), g_last.ch.grid, kind,
+                                         reps);
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: %s", who, hipGetErrorString(e));
+    return CCL_OK;
+}
+
 int ccl_copy_bytes(const void* src, void* dst, int64_t bytes, void* stream)
 {
     g_err.clear();
@@ -989,6 +1025,24 @@ int ccl_copy_bytes(const void* src, void* dst, int64_t bytes, void* stream)
     hipError_t e =
         r64::launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream), active_timer());
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "ccl_copy_bytes: %s", hipGetErrorString(e));
+    return CCL_OK;
+}
+
+int ccl_copy_segments(const void* src, void* dst, int64_t bytes, int32_t segment_bytes,
+                      int64_t src_stride_bytes, void* stream)
+{
+    g_err.clear();
+    if (bytes < 0 || (bytes > 0 && (!src || !dst)) || segment_bytes <= 0 ||
+        src_stride_bytes < segment_bytes)
+        return fail(CCL_ERR_INVALID_ARG, "ccl_copy_segments: bad arguments");
+    if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)bytes | (uintptr_t)segment_bytes |
+         (uintptr_t)src_stride_bytes) % 16 || bytes % segment_bytes)
+        return fail(CCL_ERR_INVALID_ARG, "ccl_copy_segments: pointers, sizes and stride must be "
+                    "16-byte aligned, and bytes a multiple of the segment");
+    if (bytes == 0) return CCL_OK;
+    hipError_t e = r64::launch_copy_segments(src, dst, bytes, segment_bytes, src_stride_bytes,
+                                             static_cast<hipStream_t>(stream), active_timer());
+    if (e != hipSuccess) return fail(CCL_ERR_HIP, "ccl_copy_segments: %s", hipGetErrorString(e));
     return CCL_OK;
 }
 

@@ -216,6 +216,10 @@ struct ShapeOps {
     hipError_t (*label)(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
                         KernelTimer* timer, bool local_only, GridChoice grid,
                         const StatsWs* stats);
+    // `reps` back-to-back launches of one kernel of a labelling (KIND_LOCAL
+    // or KIND_FINAL) with the arguments and launch shape `label` used.
+    hipError_t (*replay)(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
+                         GridChoice grid, int kind, int reps);
 };
 
 namespace r32 {
@@ -238,6 +242,10 @@ hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st);
 hipError_t launch_zero_count(int64_t* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,
                        KernelTimer* timer);
+// Segments of seg_bytes (a multiple of 16), one every src_stride bytes of src,
+// gathered into dst.
+hipError_t launch_copy_segments(const void* src, void* dst, int64_t bytes, int seg_bytes,
+                                int64_t src_stride, hipStream_t st, KernelTimer* timer);
 }  // namespace r64
 
 }  // namespace ccl

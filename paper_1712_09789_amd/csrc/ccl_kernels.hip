@@ -405,7 +405,6 @@ __device__ __forceinline__ void list_runs(const Lines<D>& sh, uint16_t* RL, int 
 template <int D>
 struct LocalShared : Lines<D> {
     uint32_t P[Geo<D>::MAXR];    // parent of each run, packed (key << 16) | id
-    uint16_t RL[Geo<D>::MAXR];   // run record: start column | line << 6
     uint32_t nedges;             // refinement edges listed so far
     union {
         uint32_t EL[Geo<D>::MAXE];     // refinement edge: lower run | upper run << 16
@@ -573,47 +572,38 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
     __syncthreads();
     build_lines<D>(sh, tid);
 
-    // The heavy phases below walk dense run ids (thread tid takes ids tid,
-    // tid + 256, ...) so that every lane has work; only two cheap passes walk
-    // the bits of a column window: the run list and the refinement edge list.
+    // Two passes walk the bits of a column window (the runs that start in it,
+    // and its edges to the line above); the union-find passes walk dense run
+    // ids (thread tid takes ids tid, tid + NT, ...) so that every lane has
+    // work.
     const uint32_t R = sh.base[G::NL];
     if (tid == 0) ws.nruns[T] = R;
     const int wl = tid / G::TPL;              // this thread's line
     const int wlo = (tid % G::TPL) * G::WIN;  // and first column of its window
     constexpr uint32_t WMASK = (1u << G::WIN) - 1u;
-    list_runs<D>(sh, sh.RL, tid);
+    // Row connection (Section 3.1.2): every run is one provisional label,
+    // keyed by its smallest pixel (the paper's provisional label =
+    // position).  Each thread takes the runs that start in its window.
+    {
+        const uint64_t ls = sh.LS[wl], lm = sh.LM[wl];
+        uint32_t id = sh.base[wl] + popc64(ls & ~(~0ull << wlo));
+        for (uint32_t r = (uint32_t)(ls >> wlo) & WMASK; r; r &= r - 1u, ++id) {
+            const int s0 = __builtin_ctz(r) + wlo;
+            uint32_t key;
+            if (!D) {
+                key = (uint32_t)(wl * TW + s0);
+            } else {
+                // first top-row pixel of the strip run, else its bottom-row start
+                const int len = ctz64_or64(~(lm >> s0));
+                const int tf = ctz64_or64(sh.M[2 * wl] >> s0);
+                key = tf < len ? (uint32_t)(2 * wl * TW + s0 + tf)
+                               : (uint32_t)((2 * wl + 1) * TW + s0);
+            }
+            sh.P[id] = pk(key, id);
+        }
+    }
     if (tid == 0) sh.nedges = 0u;
     __syncthreads();
-
-    // Row connection and column connection (coarse), one pass over the runs.
-    // A run is a provisional label keyed by its smallest pixel (the paper's
-    // provisional label = position); a run that touches the line above
-    // records the lowest label among its neighbours there instead, i.e. the
-    // run holding the leftmost pixel of that line's facing row that touches
-    // it.  One plain store per run: every entry is written by its owner only.
-    for (uint32_t id = tid; id < R; id += NT) {
-        const uint32_t rec = sh.RL[id];
-        const int s0 = rec & 63, l = rec >> 6;
-        const uint64_t lm = sh.LM[l];
-        const int e = s0 + ctz64_or64(~(lm >> s0)) - 1;
-        uint32_t v = pk(run_key<D>(sh, l, s0, e), id);
-        if (l > 0) {
-            const uint64_t mt = top_row<D>(sh, l) & span_mask(s0, e);
-            const uint64_t reach = D ? (mt | (mt << 1) | (mt >> 1)) : mt;
-            const uint64_t contact = bottom_row<D>(sh, l - 1) & reach;
-            if (contact) {
-                const uint64_t below = sh.LS[l - 1] & upto(ctz64(contact));
-                const int c = msb64(below);
-                const int ce = c + ctz64_or64(~(sh.LM[l - 1] >> c)) - 1;
-                v = pk(run_key<D>(sh, l - 1, c, ce), sh.base[l - 1] + popc64(below) - 1u);
-            }
-        }
-        sh.P[id] = v;
-    }
-    __syncthreads();
-
-    // Label-equivalence unification: every run points at its current root.
-    for (uint32_t id = tid; id < R; id += NT) lds_st(sh.P + id, pfind(sh.P, id));
 
     // Refinement edges: every adjacency between a line and the one above that
     // the coarse links do not already hold.  They are enumerated bitwise from
@@ -637,20 +627,20 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
         const int l = wl;
         const uint64_t T = top_row<D>(sh, l), B = bottom_row<D>(sh, l - 1);
         const uint64_t lm = sh.LM[l], lsl = sh.LS[l], lsu = sh.LS[l - 1];
-        uint64_t c0, c1 = 0, c2 = 0;
+        uint64_t c0, c1 = 0, c2 = 0, e0, e2 = 0, first;
         if (!D) {
             const uint64_t o = T & B;
-            const uint64_t e0 = o & ~(o << 1);
+            e0 = o & ~(o << 1);
             const uint64_t q = lm & ~e0;
-            const uint64_t first = (lsl & e0) | ((q + (lsl & q)) & e0);
+            first = (lsl & e0) | ((q + (lsl & q)) & e0);
             c0 = e0 & ~first;
         } else {
-            const uint64_t e0 = T & B & ~(T << 1) & ~(B << 1);
+            e0 = T & B & ~(T << 1) & ~(B << 1);
             const uint64_t e1 = (T << 1) & B & ~(B << 1);  // index = upper pixel
-            const uint64_t e2 = T & (B << 1) & ~(T << 1);
+            e2 = T & (B << 1) & ~(T << 1);
             const uint64_t x = e0 | e2 | (e1 >> 1);         // lower pixels with an edge
             const uint64_t q = lm & ~x;
-            const uint64_t first = (lsl & x) | ((q + (lsl & q)) & x);
+            first = (lsl & x) | ((q + (lsl & q)) & x);
             c0 = e0 & ~(first & e0);
             c2 = e2 & ~(first & e2);
             c1 = e1 & ~((first & ~e0 & ~e2) << 1);
@@ -663,6 +653,20 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
         const uint64_t left = ~(~0ull << wlo);
         prel = sh.base[l] + popc64(lsl & left) - 1u;
         preu = sh.base[l - 1] + popc64(lsu & left) - 1u;
+        // Column connection (coarse, Section 3.1.2): a run's first edge
+        // joins it to the run holding its leftmost neighbour in the line
+        // above; the run takes that run's current entry (its label or, if
+        // that run was linked meanwhile, an ancestor with a smaller key).
+        // Every run has at most one first edge, so every entry still has
+        // one writer.
+        for (uint32_t f = (uint32_t)(first >> wlo) & WMASK; f; f &= f - 1u) {
+            const int j = __builtin_ctz(f), p = wlo + j;
+            int u = p;  // upper pixel: same column, one left (i, i-1) or one right (i-1, i)
+            if (D && !((e0 >> p) & 1ull)) u = ((e2 >> p) & 1ull) ? p - 1 : p + 1;
+            const uint32_t lo = prel + __builtin_popcount(lslw & ((2u << j) - 1u));
+            const uint32_t up = sh.base[l - 1] + popc64(lsu & upto(u)) - 1u;
+            lds_st(sh.P + lo, lds_ld(sh.P + up));
+        }
     }
     // At most one edge per column, so the edge count of the window is a
     // popcount; edges go to the list in any order.
@@ -680,6 +684,14 @@ __device__ void local_tile(const ImageArgs& a, const Workspace& ws, LocalShared<
     }
     __syncthreads();
     const uint32_t E = sh.nedges;
+
+    // Label-equivalence unification: every run points at its current root
+    // (the coarse links form chains down the lines), so that the
+    // refinement's finds start from short paths.  The store is an atomic
+    // min: a merge of the refinement may already have linked that run.
+    for (uint32_t id = tid; id < R; id += NT)
+        __hip_atomic_fetch_min(sh.P + id, pfind(sh.P, id), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
 
     // Refinement: the paper's merge on every listed edge.
     for (uint32_t k = tid; k < E; k += NT) {
@@ -2104,6 +2116,18 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
         dst[i] = src[i];
 }
 
+// Gathers segments of seg16 16-byte units, one every sstride16 units of src,
+// into dst (contiguous): reads in requests of one segment each, as k_local
+// reads a tile's rows.
+__global__ __launch_bounds__(256) void k_copy_seg(const uint4* __restrict__ src,
+                                                  uint4* __restrict__ dst, int64_t n16,
+                                                  int seg16, int64_t sstride16)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[(i / seg16) * sstride16 + i % seg16];
+}
+
 #endif  // CCL_TILE_ROWS == 64
 
 // ---------------------------------------------------------------------------
@@ -2240,9 +2264,34 @@ hipError_t launch_label(const BatchArgs& b, int conn, const Workspace& ws, hipSt
     return launch_all<0>(b, ws, st, timer, local_only, grid, stats);
 }
 
+template <int D>
+static hipError_t replay_all(const BatchArgs& b, const Workspace& ws, hipStream_t st,
+                             GridChoice grid, int kind, int reps)
+{
+    if (b.ntiles <= 0) return hipSuccess;
+    if (kind == KIND_LOCAL) {
+        const unsigned g = tile_grid(0, b, resident_blocks(k_local<D>, NT), grid);
+        for (int r = 0; r < reps; ++r) k_local<D><<<g, NT, 0, st>>>(b, ws);
+    } else if (kind == KIND_FINAL) {
+        const unsigned g = tile_grid(1, b, resident_blocks(k_final<D, false, false>, NT), grid);
+        for (int r = 0; r < reps; ++r) k_final<D, false, false><<<g, NT, 0, st>>>(b, ws, StatsWs{});
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_replay(const BatchArgs& b, int conn, const Workspace& ws, hipStream_t st,
+                         GridChoice grid, int kind, int reps)
+{
+    if (conn == 8) return replay_all<1>(b, ws, st, grid, kind, reps);
+    return replay_all<0>(b, ws, st, grid, kind, reps);
+}
+
 // The launcher table is host data (the device pass does not see it).
 #if !defined(__HIP_DEVICE_COMPILE__)
-const ShapeOps ops = {TILE_ROWS, image_groups, image_seam_items, launch_index, launch_label};
+const ShapeOps ops = {TILE_ROWS, image_groups, image_seam_items, launch_index, launch_label,
+                      launch_replay};
 #endif
 
 #if CCL_TILE_ROWS == 64
@@ -2282,6 +2331,21 @@ hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st)
 hipError_t launch_zero_count(int64_t* count, hipStream_t st)
 {
     k_zero_count<<<1, 1, 0, st>>>(count);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_segments(const void* src, void* dst, int64_t bytes, int seg_bytes,
+                                int64_t src_stride, hipStream_t st, KernelTimer* timer)
+{
+    const int64_t n16 = bytes / 16;
+    int64_t blocks = (n16 + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    timer_begin(timer, KIND_COPY, st);
+    k_copy_seg<<<(unsigned)blocks, 256, 0, st>>>(static_cast<const uint4*>(src),
+                                                 static_cast<uint4*>(dst), n16, seg_bytes / 16,
+                                                 src_stride / 16);
+    timer_end(timer, KIND_COPY, st);
     return hipGetLastError();
 }
 

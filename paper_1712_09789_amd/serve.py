@@ -106,6 +106,11 @@ class Scheduler:
     one finishes on the device, is marked cancelled, and its labels go back
     to the pool at retirement."""
 
+    # free device memory is re-queried at most this often while it admits
+    # (the query is a driver call); a request that the last reading would
+    # refuse always gets a fresh one
+    FREE_MAX_AGE_S = 0.002
+
     def __init__(self, executor, slots: int = 4, max_batch: int = 64,
                  budget_bytes: int | None = None, clock: Callable[[], float] = time.perf_counter,
                  keep_labels: bool = True):
@@ -124,6 +129,7 @@ class Scheduler:
         self.rejected: list[Request] = []
         self.timed_out: list[Request] = []
         self.cancelled: list[Request] = []
+        self.with_deadline = 0                    # waiting or admitted requests with a deadline
         self.launches = 0
         self.launched_reqs = 0
         self.max_in_flight = 0
@@ -150,6 +156,8 @@ class Scheduler:
             req.rejected = f"needs {need} bytes, budget {self.budget}"
             self.rejected.append(req)
             return
+        if req.deadline is not None:
+            self.with_deadline += 1
         self.waiting.append(req)
 
     def _drop_labels(self, r: Request) -> None:
@@ -185,6 +193,8 @@ class Scheduler:
 
     def expire(self) -> int:
         """Drop waiting or admitted requests whose deadline has passed."""
+        if not self.with_deadline:
+            return 0
         now = self.clock()
         late = [r for r in list(self.waiting) + self.ready
                 if r.deadline is not None and now - r.arrival > r.deadline]
@@ -212,6 +222,8 @@ class Scheduler:
 
     def _unqueue(self, r: Request, status: str) -> None:
         r.status = status
+        if r.deadline is not None:
+            self.with_deadline -= 1
         if r in self.waiting:
             self.waiting.remove(r)
             return
@@ -239,9 +251,11 @@ class Scheduler:
                 if self.used_bytes + cost > self.budget:
                     break
             if free is None:
-                free = self.ex.free_bytes()
+                free = self.ex.free_bytes(max_age_s=self.FREE_MAX_AGE_S)
             if self.pending_bytes + cost > free:
-                break
+                free = self.ex.free_bytes()
+                if self.pending_bytes + cost > free:
+                    break
             self.waiting.popleft()
             r.cost, r.pooled = cost, pooled
             self.pending_bytes += cost
@@ -264,6 +278,8 @@ class Scheduler:
         for r in batch:
             r.launched = now
             r.status = "launched"
+            if r.deadline is not None:
+                self.with_deadline -= 1
             self.pending_bytes -= r.cost
             if r.pooled:
                 self.promised[(r.H, r.W)] -= 1
@@ -351,26 +367,43 @@ class GpuExecutor:
         self.label_bytes_held = 0
         _, total = torch.cuda.mem_get_info(self.dev)
         self.reserve = int(total * reserve_frac)
+        # host-side caches: the workspace cost of each frame shape, the
+        # library's workspace bytes on the streams (they change only when a
+        # batch is launched), and the last free-memory reading
+        self._ws_cost: dict[tuple[int, int], int] = {}
+        self._ws_held = 0
+        self._free = (-1.0, 0)
 
     def label_bytes(self, req: Request) -> int:
         return 4 * req.H * req.W
 
     def workspace_cost(self, req: Request) -> int:
-        return int(self.WS_GROWTH * self.ccl.workspace_bytes(req.H, req.W)) + self.WS_TABLE_SLACK
+        shape = (req.H, req.W)
+        c = self._ws_cost.get(shape)
+        if c is None:
+            c = int(self.WS_GROWTH * self.ccl.workspace_bytes(req.H, req.W)) + self.WS_TABLE_SLACK
+            self._ws_cost[shape] = c
+        return c
 
     def pooled(self, shape) -> int:
         return len(self.pool.get(tuple(shape), ()))
 
     def held_bytes(self) -> int:
-        ws = sum(self.ccl.workspace_cached(st) for st in self.streams)
-        return self.label_bytes_held + ws
+        return self.label_bytes_held + self._ws_held
 
-    def free_bytes(self) -> int:
-        """Free device memory now, less a reserve kept for everything else."""
+    def free_bytes(self, max_age_s: float = 0.0) -> int:
+        """Free device memory, less a reserve kept for everything else: a
+        reading at most max_age_s old (0 = query now)."""
+        now = time.perf_counter()
+        t, val = self._free
+        if max_age_s > 0 and now - t <= max_age_s:
+            return val
         free, _ = self.torch.cuda.mem_get_info(self.dev)
         cached = (self.torch.cuda.memory_reserved(self.dev) -
                   self.torch.cuda.memory_allocated(self.dev))
-        return max(0, int(free) + int(cached) - self.reserve)
+        val = max(0, int(free) + int(cached) - self.reserve)
+        self._free = (now, val)
+        return val
 
     def _labels(self, H, W):
         lst = self.pool.get((H, W))
@@ -405,10 +438,21 @@ class GpuExecutor:
         outs = [self._labels(r.H, r.W) for r in reqs]
         # the inputs were written on the current stream: order this stream after it
         st.wait_stream(self.torch.cuda.current_stream(self.dev))
-        self.ccl.label_batch([r.image for r in reqs], [r.connectivity for r in reqs],
-                             outs=outs, stream=st)
+        # one descriptor per frame: the image's pointer, size and pitch are
+        # checked and read once per request, not at every launch
+        descs = (self.ccl.ImageDesc * len(reqs))()
+        for i, (r, o) in enumerate(zip(reqs, outs)):
+            d = r.__dict__.get("_desc")
+            if d is None:
+                H, W, pitch = self.ccl._image_args(r.image)
+                d = r.__dict__["_desc"] = (r.image.data_ptr(), H, W, pitch, int(r.connectivity))
+            descs[i] = self.ccl.ImageDesc(d[0], d[1], d[2], d[3], d[4], o.data_ptr())
+        self.ccl._check(self.ccl.lib().ccl_label_batch(descs, len(reqs), int(st.cuda_stream)))
         ev = self.torch.cuda.Event()
         ev.record(st)
+        # the call may have grown this stream's workspace
+        self._ws_held = sum(self.ccl.workspace_cached(s) for s in self.streams)
+        self._free = (-1.0, 0)
         return (ev, outs)
 
     def done(self, handle) -> bool:

@@ -186,6 +186,21 @@ def test_noalloc_size_limit(lib):
     assert f(FAKE_IMG, 1, (1 << 31) - 1, (1 << 31) - 1, 8, FAKE_OUT + (1 << 33), None) == -2
 
 
+def test_replay_and_segment_copy_validation(lib):
+    import paper_1712_09789_amd.ccl as c
+    L = c.lib()
+    for kind in (-1, 1, 3, 4, 5, 6):
+        assert L.ccl_replay_last(kind, 1, None) == -1
+    assert L.ccl_replay_last(0, -1, None) == -1
+    # no labelling call has been made on this thread
+    assert L.ccl_replay_last(0, 1, None) == -1
+    assert b"no labelling call" in L.ccl_last_error()
+    assert L.ccl_copy_segments(FAKE_IMG, FAKE_OUT, 4096, 48, 256, None) == -1  # 48 % 16 ok, 4096 % 48
+    assert L.ccl_copy_segments(FAKE_IMG, FAKE_OUT, 4096, 64, 32, None) == -1   # stride < segment
+    assert L.ccl_copy_segments(FAKE_IMG + 8, FAKE_OUT, 4096, 64, 256, None) == -1
+    assert L.ccl_copy_segments(None, None, 0, 64, 256, None) == 0
+
+
 def test_copy_validation(lib):
     import paper_1712_09789_amd.ccl as c
     assert c.lib().ccl_copy_bytes(FAKE_IMG, FAKE_OUT, 15, None) == -1

@@ -467,3 +467,32 @@ def test_plan_and_graph_replay(ccl):
         for n, c, o in zip(new, conns, outs):
             assert np.array_equal(o.cpu().numpy(), oracle_label(n, c)), rep
     plan.close()
+
+
+def test_replay_hook_keeps_labels(ccl):
+    """ccl_replay_last (the bench's per-kernel timer): replaying the final
+    relabel rewrites the same labels; after replaying the local step the next
+    full call gives the oracle's labels again."""
+    img = wl.bernoulli(1000, 1300, 0.55, seed=77)
+    want = oracle_label(img, 8)
+    d = to_dev(img)
+    out = ccl.label(d, 8)
+    ccl.replay_last("final", 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    ccl.replay_last("local", 2)
+    ccl.label(d, 8, out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    with pytest.raises(ccl.CCLError):
+        ccl.replay_last("merge" if "merge" in ccl.KERNEL_KINDS else "seam", 1)
+
+
+def test_segment_copy(ccl):
+    """The gathering copy used to calibrate FETCH_SIZE for 64-byte requests."""
+    src = torch.randint(0, 256, (1 << 20,), dtype=torch.uint8, device="cuda")
+    dst = torch.empty(1 << 18, dtype=torch.uint8, device="cuda")
+    ccl.copy_segments(src, dst, 64, 256)
+    torch.cuda.synchronize()
+    want = src.view(-1, 256)[:, :64].reshape(-1)
+    assert torch.equal(dst, want)

@@ -65,7 +65,7 @@ class FakeExecutor:
     def held_bytes(self):
         return self.allocated
 
-    def free_bytes(self):
+    def free_bytes(self, max_age_s=0.0):
         return self.device_total - self.allocated
 
     def release(self, labels):
