@@ -304,10 +304,11 @@ int ccl_release_workspace(int32_t device);
  * around every kernel of the kinds whose bit is set in `mask` (bit k = kind
  * k; 0 stops recording).  Kinds: 0 = local step, 1 = merge across tile
  * groups, 2 = final relabel, 3 = copy, 4 = merge inside tile groups,
- * 5 = the statistics kernels of ccl_label_stats (one interval per call).
+ * 5 = the statistics kernels of ccl_label_stats (one interval per call),
+ * 6 = the merge across slices of ccl_label_3d, 7 = its final relabel.
  * ccl_timing_read() waits for the recorded events and fills, for each kind
  * k < n, the summed milliseconds ms[k] and launch count launches[k].
- * Returns the number of kinds (6).
+ * Returns the number of kinds (8).
  */
 int ccl_timing_enable(int32_t enable);
 int ccl_timing_read(double* ms, int64_t* launches, int32_t n);

@@ -706,7 +706,7 @@ int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pi
     v.H = H;
     v.W = W;
     v.vec = ((uintptr_t)labels & 15) == 0;
-    hipError_t e = r64::launch_volume(v, connectivity, st);
+    hipError_t e = r64::launch_volume(v, connectivity, st, active_timer());
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
     return CCL_OK;
 }

@@ -186,7 +186,7 @@ inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
 
 enum {
     KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, KIND_BLOCK = 4,
-    KIND_STATS = 5, NKINDS = 6
+    KIND_STATS = 5, KIND_ZMERGE = 6, KIND_ZFINAL = 7, NKINDS = 8
 };
 
 struct KernelTimer;  // host-side event recorder, null when timing is off
@@ -237,7 +237,7 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
                            uint32_t* counters);
 // Unite components across adjacent slices of a volume (6- or 26-connectivity)
 // and write canonical labels; the slices' labels must already be in place.
-hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st);
+hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st, KernelTimer* timer);
 // Writes *count = 0 (an empty image has no components).
 hipError_t launch_zero_count(int64_t* count, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st,

@@ -2314,16 +2314,20 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st)
+hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st, KernelTimer* timer)
 {
     const int64_t S = (int64_t)v.H * v.W, n = (int64_t)v.D * S;
     if (n == 0) return hipSuccess;
     if (v.D > 1) {
         const int nbx = (v.W + ZB_W - 1) / ZB_W, nby = (v.H + ZB_H - 1) / ZB_H;
         const unsigned g = (unsigned)((int64_t)(v.D - 1) * nbx * nby);
+        timer_begin(timer, KIND_ZMERGE, st);
         if (conn == 26) k_zmerge<26><<<g, 256, 0, st>>>(v, nbx, nby);
         else k_zmerge<6><<<g, 256, 0, st>>>(v, nbx, nby);
+        timer_end(timer, KIND_ZMERGE, st);
+        timer_begin(timer, KIND_ZFINAL, st);
         k_zfinal<<<(unsigned)((n / 4 + 256) / 256), 256, 0, st>>>(v);
+        timer_end(timer, KIND_ZFINAL, st);
     }
     return hipGetLastError();
 }

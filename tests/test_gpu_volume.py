@@ -102,3 +102,18 @@ def _edge_patterns():
 @pytest.mark.parametrize("name", ["diagonals", "rows", "cols"])
 def test_block_edge_contacts(ccl, name, conn):
     check(ccl, _edge_patterns()[name], conn, name)
+
+
+@pytest.mark.parametrize("D", [6, 16])
+def test_more_slice_labels_than_merge_table(ccl, D):
+    # A 2-D checkerboard repeated on every slice: under 6-connectivity every
+    # foreground voxel is its own slice component and touches the voxel of
+    # the next slice, so every block of a slice pair holds the most distinct
+    # slice labels a block can (one per voxel of half its columns), and the
+    # merge across slices unites 512 pairs per 64 x 16 block.
+    H, W = 48, 200
+    y, x = np.mgrid[0:H, 0:W]
+    vol = np.broadcast_to(((x + y) % 2 == 0).astype(np.uint8), (D, H, W)).copy()
+    vol[D // 2, 5:9, 10:190] = 1  # one slice joins a band of columns in-slice
+    check(ccl, vol, 6, "checkerboard columns")
+    check(ccl, vol, 26, "checkerboard columns")
