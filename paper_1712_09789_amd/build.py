@@ -2,6 +2,8 @@
 
 ``python -m paper_1712_09789_amd.build`` compiles the kernels and the C-ABI
 host code with hipcc and links them in-tree, next to this file.
+The host-sanitized variant for the CPU tests is built by
+``build_sanitized.py``.
 """
 from __future__ import annotations
 

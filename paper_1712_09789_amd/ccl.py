@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libccl.so")
+# CCL_LIBRARY names another build of the library (the sanitized host build)
+LIB_PATH = os.environ.get("CCL_LIBRARY") or os.path.join(_HERE, "libccl.so")
 
 CCL_OK = 0
 STATUS_NAMES = {0: "CCL_OK", -1: "CCL_ERR_INVALID_ARG", -2: "CCL_ERR_TOO_LARGE",

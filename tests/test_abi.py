@@ -8,7 +8,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ccl.h")
-LIB = os.path.join(ROOT, "paper_1712_09789_amd", "libccl.so")
+LIB = os.environ.get("CCL_LIBRARY") or os.path.join(ROOT, "paper_1712_09789_amd", "libccl.so")
 
 
 def declared_functions():
