@@ -481,7 +481,7 @@ def bench_volume(ccl, torch, dev, check=True, n=512, reps=10):
             e1.record(st)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
-            ccl.timing_enable(True, ("zmerge", "zfinal"))
+            ccl.timing_enable(True, ("vlocal", "vmerge", "vfinal"))
             for _ in range(reps):
                 ccl.label_3d(vol, conn, out=lab)
             t = ccl.timing_read()
@@ -489,7 +489,7 @@ def bench_volume(ccl, torch, dev, check=True, n=512, reps=10):
             out[f"{kind}{kw} conn={conn}"] = {
                 "Gvox/s": round(n ** 3 / ms / 1e6, 1), "us": round(1e3 * ms, 1),
                 "kernel_avg_us": {k: round(1e3 * t[k][0] / t[k][1], 1)
-                                  for k in ("zmerge", "zfinal") if t[k][1]}}
+                                  for k in ("vlocal", "vmerge", "vfinal") if t[k][1]}}
         del vol
     del lab
     torch.cuda.empty_cache()

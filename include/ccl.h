@@ -182,10 +182,11 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
 /*
  * Label a volume (the paper's introduction names 2-D and 3-D images): voxel
  * position P = x + y * W + z * W * H; labels[P] = 0 for background, else 1 +
- * the smallest position in the voxel's component.  The slices are labelled
- * with the 2-D method (one batch), then components are united across
- * adjacent slices (the block merge with slices as blocks) and every label is
- * rewritten to its root.
+ * the smallest position in the voxel's component.  The paper's method with
+ * a third axis: bricks of 64 x 8 x 8 voxels (x, y, z) are labelled in LDS
+ * (runs along x united across the brick's rows and slices), components are
+ * united across brick faces in the label map (the block merge), and every
+ * label is rewritten to its root.  No workspace.
  *   vol           device, uint8, D slices of H rows; row y of slice z starts
  *                 at vol + z * slice_pitch_bytes + y * pitch_bytes;
  *                 caller-owned, only read.
@@ -194,9 +195,8 @@ int ccl_label_stats(const uint8_t* img, int32_t H, int32_t W, int64_t pitch_byte
  *   connectivity  6 (face neighbours) or 26 (the 3 x 3 x 3 block).
  *   labels        device, int32, dense D * H * W; caller-owned, fully
  *                 overwritten.  Must not overlap vol.
- * Errors as ccl_label (CCL_ERR_TOO_LARGE when D * H * W > 2^31 - 1, or when
- * the D slices together have more than (2^31 - 1) / 256 tiles of the built-in
- * shape, as very thin slices can); an empty volume is a no-op.
+ * Errors as ccl_label (CCL_ERR_TOO_LARGE when D * H * W > 2^31 - 1); an
+ * empty volume is a no-op.
  */
 int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pitch_bytes,
                  int64_t slice_pitch_bytes, int32_t connectivity, int32_t* labels, void* stream);
@@ -305,10 +305,11 @@ int ccl_release_workspace(int32_t device);
  * k; 0 stops recording).  Kinds: 0 = local step, 1 = merge across tile
  * groups, 2 = final relabel, 3 = copy, 4 = merge inside tile groups,
  * 5 = the statistics kernels of ccl_label_stats (one interval per call),
- * 6 = the merge across slices of ccl_label_3d, 7 = its final relabel.
+ * 6 = the merge across brick faces of ccl_label_3d, 7 = its final relabel,
+ * 8 = its local step (bricks).
  * ccl_timing_read() waits for the recorded events and fills, for each kind
  * k < n, the summed milliseconds ms[k] and launch count launches[k].
- * Returns the number of kinds (8).
+ * Returns the number of kinds (9).
  */
 int ccl_timing_enable(int32_t enable);
 int ccl_timing_read(double* ms, int64_t* launches, int32_t n);

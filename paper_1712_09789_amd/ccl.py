@@ -21,7 +21,8 @@ LIB_PATH = os.environ.get("CCL_LIBRARY") or os.path.join(_HERE, "libccl.so")
 CCL_OK = 0
 STATUS_NAMES = {0: "CCL_OK", -1: "CCL_ERR_INVALID_ARG", -2: "CCL_ERR_TOO_LARGE",
                 -3: "CCL_ERR_OUT_OF_MEMORY", -4: "CCL_ERR_HIP"}
-KERNEL_KINDS = ("local", "seam", "final", "copy", "block", "stats", "zmerge", "zfinal")
+KERNEL_KINDS = ("local", "seam", "final", "copy", "block", "stats", "vmerge", "vfinal",
+                "vlocal")
 # Layout of ccl_component (include/ccl.h), 40 bytes per component.
 COMPONENT_DTYPE = np.dtype([("label", np.int32), ("area", np.int32),
                             ("x_min", np.int32), ("y_min", np.int32),

@@ -684,27 +684,18 @@ int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pi
                                           (int64_t)(H - 1) * pitch_bytes + W);
     const uintptr_t l0 = (uintptr_t)labels, l1 = l0 + (uintptr_t)((int64_t)D * H * W * 4);
     if (v0 < l1 && l0 < v1) return fail(CCL_ERR_INVALID_ARG, "%s: vol and labels overlap", who);
-    const int64_t tiles = (int64_t)D * tiles_of(H, W, DEFAULT_ROWS);
-    if (!node_ids_fit(tiles, DEFAULT_ROWS))
-        return fail(CCL_ERR_TOO_LARGE, "%s: %lld tiles over all slices exceed the node id range",
-                    who, (long long)tiles);
-    const int conn2 = connectivity == 6 ? 4 : 8;  // the in-slice part of the neighbourhood
-    std::vector<ImageArgs> slices;
-    slices.reserve(D);
-    for (int32_t z = 0; z < D; ++z) {
-        ImageArgs a = make_args(vol + (int64_t)z * slice_pitch_bytes, H, W, pitch_bytes,
-                                labels + (int64_t)z * H * W, DEFAULT_ROWS);
-        a.lbase = (int32_t)((int64_t)z * H * W);
-        slices.push_back(a);
-    }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int rc = run_batch(slices, conn2, builtin_choice(), st, false, who);
-    if (rc != CCL_OK) return rc;
     VolArgs v;
+    v.vol = vol;
+    v.pitch = pitch_bytes;
+    v.spitch = D > 1 ? slice_pitch_bytes : 0;
     v.labels = labels;
     v.D = D;
     v.H = H;
     v.W = W;
+    v.nbx = (W + VOL_BRICK_W - 1) / VOL_BRICK_W;
+    v.nby = (H + VOL_BRICK_H - 1) / VOL_BRICK_H;
+    v.nbz = (D + VOL_BRICK_D - 1) / VOL_BRICK_D;
     v.vec = ((uintptr_t)labels & 15) == 0;
     hipError_t e = r64::launch_volume(v, connectivity, st, active_timer());
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));

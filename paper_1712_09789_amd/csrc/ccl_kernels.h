@@ -48,10 +48,14 @@ static_assert(sizeof(ImageArgs) == 64, "ImageArgs is one 64-byte scalar load");
 // voxel positions by lbase); the labels alone carry what the merge across
 // slices needs (nonzero exactly on foreground).
 struct VolArgs {
-    int32_t* labels;  // dense D x H x W
+    const uint8_t* vol;     // voxel (z, y, x) at vol[z * spitch + y * pitch + x]
+    int64_t pitch, spitch;  // bytes between rows / slices
+    int32_t* labels;        // dense D x H x W
     int32_t D, H, W;
-    int32_t vec;      // labels is 16-byte aligned
+    int32_t nbx, nby, nbz;  // bricks along x, y, z
+    int32_t vec;            // labels is 16-byte aligned
 };
+constexpr int VOL_BRICK_W = 64, VOL_BRICK_H = 8, VOL_BRICK_D = 8;  // voxels per brick (x, y, z)
 
 // Images labelled by one set of launches (all of one connectivity).  With n
 // == 1 the image travels in `one` and the tables are unused; otherwise the
@@ -186,7 +190,7 @@ inline StatsWs carve_stats(void* base, int64_t ntiles, int ntx, int nty)
 
 enum {
     KIND_LOCAL = 0, KIND_SEAM = 1, KIND_FINAL = 2, KIND_COPY = 3, KIND_BLOCK = 4,
-    KIND_STATS = 5, KIND_ZMERGE = 6, KIND_ZFINAL = 7, NKINDS = 8
+    KIND_STATS = 5, KIND_VMERGE = 6, KIND_VFINAL = 7, KIND_VLOCAL = 8, NKINDS = 9
 };
 
 struct KernelTimer;  // host-side event recorder, null when timing is off

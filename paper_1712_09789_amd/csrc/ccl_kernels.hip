@@ -522,6 +522,18 @@ struct Chunk {
     uint32_t off;   // byte of the segment's first pixel in lo
     uint32_t n;     // pixels of the segment inside the image (0 .. 16)
 };
+// n (1 .. 16) pixels from src, through the aligned blocks that hold them.
+__device__ __forceinline__ Chunk fetch_segment(const uint8_t* src, uint32_t n)
+{
+    Chunk k;
+    k.hi = make_uint4(0u, 0u, 0u, 0u);
+    k.n = n;
+    k.off = (uint32_t)((uintptr_t)src & 15u);
+    const uint8_t* blk = src - k.off;
+    k.lo = ld_global16(blk);
+    if (k.off + k.n > 16u) k.hi = ld_global16(blk + 16);
+    return k;
+}
 __device__ __forceinline__ Chunk fetch_chunk(const ImageArgs& a, int t, int c)
 {
     const int gx = (t % a.ntx) * TW + 16 * (c & 3);
@@ -529,14 +541,9 @@ __device__ __forceinline__ Chunk fetch_chunk(const ImageArgs& a, int t, int c)
     Chunk k;
     k.lo = k.hi = make_uint4(0u, 0u, 0u, 0u);
     k.off = k.n = 0u;
-    if (gy < a.H && gx < a.W) {
-        const uint8_t* src = a.img + (int64_t)gy * a.pitch + gx;
-        k.n = (uint32_t)(a.W - gx < 16 ? a.W - gx : 16);
-        k.off = (uint32_t)((uintptr_t)src & 15u);
-        const uint8_t* blk = src - k.off;
-        k.lo = ld_global16(blk);
-        if (k.off + k.n > 16u) k.hi = ld_global16(blk + 16);
-    }
+    if (gy < a.H && gx < a.W)
+        k = fetch_segment(a.img + (int64_t)gy * a.pitch + gx,
+                          (uint32_t)(a.W - gx < 16 ? a.W - gx : 16));
     return k;
 }
 
@@ -1905,13 +1912,25 @@ __global__ __launch_bounds__(NT) void k_local_ablate(BatchArgs b, Workspace ws, 
 // volumes
 // ---------------------------------------------------------------------------
 
-// The slices of a volume are labelled as a batch of images (4-connectivity
-// for 6, 8 for 26: the in-slice part of the neighbourhood), each label
-// lifted to 1 + a voxel position.  The label map is then itself the forest
-// of the merge across slices (the paper's block merge, with slices as the
-// blocks): every voxel's entry is 1 + an ancestor's position, the smallest
-// voxel of each slice component starts as a root, and a merge points the
-// larger root at the smaller with an atomic min, so entries only decrease.
+// The paper's method with a third axis (Section 3 lifted to 3-D): the
+// volume is cut into bricks of 64 x VB_H x VB_D voxels (x, y, z), each
+// labelled on its own in LDS (runs along x, united across the rows and
+// slices of the brick), then the bricks are merged across their faces, and
+// a final pass gives every voxel its component's label.
+//
+// k_vlocal writes every voxel's provisional label: 1 + the position of the
+// smallest voxel of its component within the brick.  The label map is then
+// itself the forest of the merge: every entry is 1 + an ancestor's position,
+// the smallest voxel of each brick component is a root, and k_vmerge unites
+// components that touch across a brick face by pointing the larger root at
+// the smaller with an atomic min, so entries only decrease.  k_vfinal
+// replaces each label by its root's.
+constexpr int VB_W = VOL_BRICK_W, VB_H = VOL_BRICK_H, VB_D = VOL_BRICK_D;  // 64 rows of 64
+constexpr int VB_ROWS = VB_H * VB_D;          // brick row r = z * VB_H + y
+constexpr int VNT = 256;                      // threads per brick: 16 voxels each
+constexpr int VMAXR = VB_ROWS * (VB_W / 2);   // runs per brick, at most
+static_assert(VB_ROWS * 4 == VNT && VB_ROWS == 64, "one 16-voxel segment per thread");
+static_assert(VB_ROWS * VB_W <= 0x8000 && VMAXR <= 0x10000, "16-bit keys and run ids");
 
 // Entry of a node during the merge: the first two hops of a find use plain
 // loads, later ones coherent loads (as g_hop for the 2-D forest).
@@ -1961,108 +1980,290 @@ __device__ void v_union(int32_t* lab, uint32_t a, uint32_t b, uint32_t n)
     }
 }
 
-// k_zmerge: one workgroup per 64 x 16 block of a slice pair (z-1, z).  The
-// block's labels in both slices are staged in LDS with one 64-bit foreground
-// mask per row (a label is nonzero exactly on foreground); slice z-1 gets a
-// rim of one row and one column, which 26-connectivity reaches.  The work is
-// done per run: each maximal stretch of foreground in a block row of slice z
-// lies in one slice component, so one label names it, and it is united with
-// every run of slice z-1 it touches (again one label each): for
-// 6-connectivity the runs of the same row that share a column with it; for
-// 26 the runs in the three rows around it, one column further on each side,
-// the rim included.  A run that crosses the
-// block's edge is cut there; the two parts together touch the same runs.  A
-// thread drops a pair equal to the one it united last, and the workgroup
-// drops pairs another of its threads already holds (LDS hash, as in k_seam).
-// The staged labels may be stale (roots are lowered meanwhile): any
-// ancestor of a component serves.
-constexpr int ZB_W = 64, ZB_H = 16;  // block of a slice pair
-constexpr int ZM_HASH = 1024;
-template <int C>
-__global__ __launch_bounds__(256) void k_zmerge(VolArgs v, int nbx, int nby)
+// Brick (bx, by, bz) of workgroup / work item `i` (bricks in raster order).
+struct Brick {
+    int x0, y0, z0;
+};
+__device__ __forceinline__ Brick brick_of(const VolArgs& v, int64_t i)
 {
-    static_assert(ZB_W == 64 && ZB_H * 16 == 256, "a wave per staged row; 16 threads per block row");
-    constexpr int PR = ZB_H + 2;                 // staged rows of slice z-1: y0-1 .. y0+ZB_H
-    __shared__ int32_t plab[PR][ZB_W + 2];       // slice z-1, columns x0-1 .. x0+ZB_W
-    __shared__ int32_t clab[ZB_H][ZB_W];         // slice z, columns x0 .. x0+ZB_W-1
-    __shared__ uint64_t pm[PR], cm[ZB_H];        // foreground of columns x0 .. x0+63
-    __shared__ unsigned long long seen[ZM_HASH];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int k = tid; k < ZM_HASH; k += 256) seen[k] = ~0ull;
-    const int64_t S = (int64_t)v.H * v.W;
-    const uint32_t n = (uint32_t)((int64_t)v.D * S);
-    const int64_t per_slice = (int64_t)nbx * nby;
-    const int z = (int)(blockIdx.x / per_slice) + 1;
-    const int r = (int)(blockIdx.x - (int64_t)(z - 1) * per_slice);
-    const int x0 = (r % nbx) * ZB_W, y0 = (r / nbx) * ZB_H;
-    const int32_t* Lp = v.labels + (int64_t)(z - 1) * S;
-    const int32_t* Lc = v.labels + (int64_t)z * S;
-    // one staged row per wave step, one column per lane (wave-uniform loop)
-    for (int row = wave; row < PR + ZB_H; row += 4) {
-        const bool prev = row < PR;
-        if (C == 6 && (row == 0 || row == PR - 1)) continue;  // rim rows: 26 only
-        const int y = prev ? y0 - 1 + row : y0 + (row - PR);
-        const int x = x0 + lane;
-        int32_t val = 0;
-        if (y >= 0 && y < v.H && x < v.W) val = ld_global((prev ? Lp : Lc) + (int64_t)y * v.W + x);
-        const uint64_t m = __ballot(val != 0);
-        if (prev) {
-            plab[row][lane + 1] = val;
-            if (lane == 0) pm[row] = m;
-        } else {
-            clab[row - PR][lane] = val;
-            if (lane == 0) cm[row - PR] = m;
+    Brick k;
+    const int64_t per_slab = (int64_t)v.nbx * v.nby;
+    const int bz = (int)(i / per_slab), r = (int)(i - bz * per_slab);
+    k.x0 = (r % v.nbx) * VB_W;
+    k.y0 = (r / v.nbx) * VB_H;
+    k.z0 = bz * VB_D;
+    return k;
+}
+
+struct VolLocalShared {
+    uint64_t M[VB_ROWS];          // foreground of each brick row
+    uint64_t S[VB_ROWS];          // run starts of each row
+    uint32_t base[VB_ROWS + 1];   // id of the first run of each row; base[64] = runs
+    uint32_t P[VMAXR];            // parent of each run, packed (brick key << 16) | id
+    int32_t lab[VMAXR];           // label of each run (1 + its root's volume position)
+    uint16_t h[VNT];              // 16-voxel masks as loaded
+};
+
+// Dense id of the run of brick row r that contains foreground column x.
+__device__ __forceinline__ uint32_t vrun(const VolLocalShared& sh, int r, int x)
+{
+    return sh.base[r] + popc64(sh.S[r] & upto(x)) - 1u;
+}
+
+// Unites the runs of brick row r with those of an earlier row nr that they
+// touch, for the edges whose index lies in columns c0 .. c0+15.  Face
+// neighbours (6-connectivity: nr is the row above or the same row of the
+// slice below) touch where the rows overlap: one edge per overlapping
+// stretch.  With diagonals (26-connectivity) the edges are those of two
+// 8-connected rows: (i, i) where neither row continues from i-1, (i-1, i)
+// where nr does not continue from i-1, (i, i-1) where r does not (at most
+// one per column; for two touching runs, the edge at the larger of their
+// first columns is listed).
+// With `last` (the slice below, whose runs already point at roots of the
+// brick's slices), an edge is dropped when the two runs' current parents are
+// the pair this thread united last: the runs of the slice below that one
+// run touches mostly belong to one slice component.
+template <bool DIAG>
+__device__ __forceinline__ void vlink_rows(VolLocalShared& sh, int r, int nr, int c0,
+                                           uint32_t* last = nullptr)
+{
+    const uint64_t T = sh.M[r], B = sh.M[nr];
+    auto join = [&](uint32_t a, uint32_t b) {
+        if (last) {
+            const uint32_t pa = pk_id(lds_ld(sh.P + a)), pb = pk_id(lds_ld(sh.P + b));
+            const uint32_t pair = (pa << 16) | pb;
+            if (pair == *last) return;
+            *last = pair;
         }
+        punion(sh.P, a, b);
+    };
+    if (!DIAG) {
+        const uint64_t o = T & B;
+        for (uint32_t e = (uint32_t)((o & ~(o << 1)) >> c0) & 0xffffu; e; e &= e - 1u) {
+            const int x = __builtin_ctz(e) + c0;
+            join(vrun(sh, r, x), vrun(sh, nr, x));
+        }
+        return;
     }
-    if (C == 26 && tid < 2 * PR) {  // rim columns x0-1 and x0+64 of slice z-1
-        const int row = tid >> 1, side = tid & 1;
-        const int y = y0 - 1 + row, x = side ? x0 + ZB_W : x0 - 1;
-        plab[row][side ? ZB_W + 1 : 0] =
-            (y >= 0 && y < v.H && x >= 0 && x < v.W) ? ld_global(Lp + (int64_t)y * v.W + x) : 0;
+    const uint64_t e0 = T & B & ~(T << 1) & ~(B << 1);
+    const uint64_t e1 = (T << 1) & B & ~(B << 1);  // r at i-1, nr at i
+    const uint64_t e2 = T & (B << 1) & ~(T << 1);  // r at i, nr at i-1
+    for (uint32_t e = (uint32_t)((e0 | e1 | e2) >> c0) & 0xffffu; e; e &= e - 1u) {
+        const int i = __builtin_ctz(e) + c0;
+        const int xr = ((e1 >> i) & 1ull) ? i - 1 : i, xn = ((e2 >> i) & 1ull) ? i - 1 : i;
+        join(vrun(sh, r, xr), vrun(sh, nr, xn));
+    }
+}
+
+// k_vlocal: one workgroup per brick.  Thread tid loads sixteen voxels of
+// brick row tid / 4; every run is a provisional label keyed by its first
+// voxel (Section 3.1.2), runs are united with the runs they touch in the
+// row above and in the rows of the slice below (Section 3.1.3, the
+// neighbourhood restricted to the brick), every run then takes its root
+// (Section 3.1.4), and each voxel is written as 1 + the position of its
+// root run's first voxel, the smallest voxel of its brick component.
+template <int C>
+__global__ __launch_bounds__(VNT) void k_vlocal(VolArgs v)
+{
+    __shared__ VolLocalShared sh;
+    const int tid = threadIdx.x;
+    const Brick bk = brick_of(v, blockIdx.x);
+    const int r = tid >> 2, c0 = (tid & 3) * 16;
+    const int ky = r % VB_H, kz = r / VB_H;
+    const int x = bk.x0 + c0, y = bk.y0 + ky, z = bk.z0 + kz;
+    const bool live = z < v.D && y < v.H && x < v.W;
+    uint32_t m16 = 0u;
+    if (live) {
+        const Chunk k = fetch_segment(v.vol + (int64_t)z * v.spitch + (int64_t)y * v.pitch + x,
+                                      (uint32_t)(v.W - x < 16 ? v.W - x : 16));
+        m16 = chunk_mask(k);
+    }
+    sh.h[tid] = (uint16_t)m16;
+    __syncthreads();
+    if (tid < 64) {  // rows, run starts and run-id bases (first wavefront)
+        const uint64_t m = (uint64_t)sh.h[4 * tid] | ((uint64_t)sh.h[4 * tid + 1] << 16) |
+                           ((uint64_t)sh.h[4 * tid + 2] << 32) | ((uint64_t)sh.h[4 * tid + 3] << 48);
+        const uint64_t st = m & ~(m << 1);
+        sh.M[tid] = m;
+        sh.S[tid] = st;
+        const uint32_t cnt = popc64(st);
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if (tid >= off) inc += o;
+        }
+        sh.base[tid] = inc - cnt;
+        if (tid == 63) sh.base[VB_ROWS] = inc;
     }
     __syncthreads();
+    {  // runs starting in this thread's sixteen columns
+        const uint64_t st = sh.S[r];
+        uint32_t id = sh.base[r] + popc64(st & ~(~0ull << c0));
+        for (uint32_t w = (uint32_t)(st >> c0) & 0xffffu; w; w &= w - 1u, ++id)
+            sh.P[id] = pk((uint32_t)(r * VB_W + __builtin_ctz(w) + c0), id);
+    }
+    __syncthreads();
+    // in-slice edges first, then every run points at its slice root, so
+    // that the edges to the slice below can be deduplicated on roots
+    if (ky > 0) vlink_rows<C == 26>(sh, r, r - 1, c0);
+    __syncthreads();
+    const uint32_t R = sh.base[VB_ROWS];
+    for (uint32_t id = tid; id < R; id += VNT)
+        __hip_atomic_fetch_min(sh.P + id, pfind(sh.P, id), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    if (kz > 0) {
+        uint32_t last = ~0u;
+        if (C == 6) {
+            vlink_rows<false>(sh, r, r - VB_H, c0, &last);
+        } else {
+            if (ky > 0) vlink_rows<true>(sh, r, r - VB_H - 1, c0, &last);
+            vlink_rows<true>(sh, r, r - VB_H, c0, &last);
+            if (ky < VB_H - 1) vlink_rows<true>(sh, r, r - VB_H + 1, c0, &last);
+        }
+    }
+    __syncthreads();
+    // every run's label: 1 + the volume position of its root's first voxel
+    const int64_t S = (int64_t)v.H * v.W;
+    const int64_t org = (int64_t)bk.z0 * S + (int64_t)bk.y0 * v.W + bk.x0 + 1;
+    for (uint32_t id = tid; id < R; id += VNT) {
+        const uint32_t key = pk_key(pfind(sh.P, id));
+        const int kr = (int)(key / VB_W);
+        sh.lab[id] = (int32_t)(org + (int64_t)(kr / VB_H) * S + (int64_t)(kr % VB_H) * v.W +
+                               (int)(key % VB_W));
+    }
+    __syncthreads();
+    // Labels out: each wavefront store covers four whole brick rows (row
+    // w * 16 + 4q + lane / 16, columns 4 * (lane % 16) .. +3).
+    const int lane = tid & 63, wave = tid >> 6;
+    const int xw = 4 * (lane % 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rr = wave * 16 + 4 * q + lane / 16;
+        const int yy = bk.y0 + rr % VB_H, zz = bk.z0 + rr / VB_H, xx = bk.x0 + xw;
+        if (zz >= v.D || yy >= v.H || xx >= v.W) continue;
+        const uint64_t m = sh.M[rr];
+        int32_t o[4];
+        uint32_t id = vrun(sh, rr, xw);  // the last run starting at or left of xw
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int xj = xw + j;
+            if (j > 0 && ((m >> xj) & 1ull) && !((m >> (xj - 1)) & 1ull)) ++id;  // a run starts
+            o[j] = ((m >> xj) & 1ull) ? sh.lab[id] : 0;
+        }
+        int32_t* dst = v.labels + (int64_t)zz * S + (int64_t)yy * v.W + xx;
+        if (v.W - xx >= 4 && v.vec && (((uintptr_t)dst & 15u) == 0)) {
+            st_global16(dst, o[0], o[1], o[2], o[3]);
+        } else {
+            for (int j = 0; j < 4; ++j)
+                if (xx + j < v.W) st_global(dst + j, o[j]);
+        }
+    }
+}
+
+// k_vmerge: the merge across brick faces (Section 3.2, boundary analysis in
+// 3-D), in the label map.  One workgroup per brick takes the voxel pairs
+// that cross its three lower faces, each pair exactly once over the volume:
+//   z face (z = z0 against z0-1): every neighbour in the slice below,
+//       whatever brick it is in (26: the nine voxels around);
+//   y face (y = y0 against y0-1): neighbours in the row above within the
+//       brick's own slab of slices (26: z-1 .. z+1, x-1 .. x+1);
+//   x face (x = x0 against x0-1): neighbours in the column to the left
+//       within the brick's own slab and row band (26: z and y +-1).
+// A pair crossing several faces belongs to the first of them in that order.
+// A thread drops a pair equal to the one it united last, and the workgroup
+// drops pairs another of its threads already holds (LDS hash); labels read
+// may be stale (roots are lowered meanwhile): any ancestor serves.
+constexpr int VM_HASH = 1024;
+template <int C>
+__global__ __launch_bounds__(VNT) void k_vmerge(VolArgs v)
+{
+    __shared__ unsigned long long seen[VM_HASH];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < VM_HASH; k += VNT) seen[k] = ~0ull;
+    __syncthreads();
+    const Brick bk = brick_of(v, blockIdx.x);
+    const int64_t S = (int64_t)v.H * v.W;
+    const uint32_t n = (uint32_t)((int64_t)v.D * S);
+    const int zend = min(bk.z0 + VB_D, v.D), yend = min(bk.y0 + VB_H, v.H);
     uint32_t la = ~0u, lb = ~0u;  // the pair this thread united last
-    auto unite = [&](uint32_t a, int32_t B) {
-        const uint32_t b = (uint32_t)B - 1u;
+    auto unite = [&](int32_t A, int32_t B) {
+        const uint32_t a = (uint32_t)A - 1u, b = (uint32_t)B - 1u;
         if (a >= n || b >= n || a == b || (a == la && b == lb)) return;
         la = a;
         lb = b;
         const unsigned long long key = ((unsigned long long)a << 32) | b;
         uint32_t h = (a * 0x9e3779b1u) ^ (b * 0x85ebca77u);
         for (int probe = 0; probe < 8; ++probe, ++h) {
-            const unsigned long long old = atomicCAS(seen + (h & (ZM_HASH - 1)), ~0ull, key);
+            const unsigned long long old = atomicCAS(seen + (h & (VM_HASH - 1)), ~0ull, key);
             if (old == key) return;   // another thread of the workgroup unites this pair
             if (old == ~0ull) break;  // claimed a fresh entry
         }
         v_union(v.labels, a, b, n);
     };
-    // thread: block row ty, runs starting in columns c0 .. c0+3
-    const int ty = tid >> 4, c0 = (tid & 15) * 4;
-    const uint64_t m = cm[ty];
-    uint64_t starts = m & ~(m << 1) & (0xfull << c0);
-    while (starts) {
-        const int c = __builtin_ctzll(starts);
-        starts &= starts - 1;
-        const uint64_t rest = ~m >> c;  // bit 0 clear: column c is foreground
-        const int e = rest ? c + __builtin_ctzll(rest) - 1 : 63;
-        const uint32_t a = (uint32_t)clab[ty][c] - 1u;
-        const int lo = C == 26 ? c - 1 : c, hi = C == 26 ? e + 1 : e;  // columns touched
-        for (int pr = C == 26 ? ty : ty + 1; pr <= (C == 26 ? ty + 2 : ty + 1); ++pr) {
-            const uint64_t q = pm[pr] & span_mask(lo < 0 ? 0 : lo, hi > 63 ? 63 : hi);
-            for (uint64_t s2 = q & ~(q << 1); s2; s2 &= s2 - 1)
-                unite(a, plab[pr][__builtin_ctzll(s2) + 1]);
-            // rim voxels, unless the run through column 0 / 63 already reached them
-            if (lo < 0 && !(q & 1ull) && plab[pr][0] != 0) unite(a, plab[pr][0]);
-            if (hi > 63 && !(q >> 63) && plab[pr][ZB_W + 1] != 0) unite(a, plab[pr][ZB_W + 1]);
+    auto at = [&](int zz, int yy, int xx) {
+        return ld_global(v.labels + (int64_t)zz * S + (int64_t)yy * v.W + xx);
+    };
+    constexpr int R1 = C == 26 ? 1 : 0;  // neighbourhood radius along the other axes
+    // z face: 64 x VB_H voxels, two per thread
+    if (bk.z0 > 0) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = tid + k * VNT, xx = bk.x0 + i % VB_W, yy = bk.y0 + i / VB_W;
+            if (xx >= v.W || yy >= v.H) continue;
+            const int32_t A = at(bk.z0, yy, xx);
+            if (A == 0) continue;
+            for (int dy = -R1; dy <= R1; ++dy)
+                for (int dx = -R1; dx <= R1; ++dx) {
+                    const int y2 = yy + dy, x2 = xx + dx;
+                    if (y2 < 0 || y2 >= v.H || x2 < 0 || x2 >= v.W) continue;
+                    const int32_t B = at(bk.z0 - 1, y2, x2);
+                    if (B != 0) unite(A, B);
+                }
+        }
+    }
+    // y face: 64 x VB_D voxels, two per thread
+    if (bk.y0 > 0) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = tid + k * VNT, xx = bk.x0 + i % VB_W, zz = bk.z0 + i / VB_W;
+            if (xx >= v.W || zz >= zend) continue;
+            const int32_t A = at(zz, bk.y0, xx);
+            if (A == 0) continue;
+            for (int dz = -R1; dz <= R1; ++dz)
+                for (int dx = -R1; dx <= R1; ++dx) {
+                    const int z2 = zz + dz, x2 = xx + dx;
+                    if (z2 < bk.z0 || z2 >= zend || x2 < 0 || x2 >= v.W) continue;
+                    const int32_t B = at(z2, bk.y0 - 1, x2);
+                    if (B != 0) unite(A, B);
+                }
+        }
+    }
+    // x face: VB_H x VB_D voxels, one per thread of the first quarter
+    if (bk.x0 > 0 && tid < VB_H * VB_D) {
+        const int yy = bk.y0 + tid % VB_H, zz = bk.z0 + tid / VB_H;
+        if (yy < yend && zz < zend) {
+            const int32_t A = at(zz, yy, bk.x0);
+            if (A != 0) {
+                for (int dz = -R1; dz <= R1; ++dz)
+                    for (int dy = -R1; dy <= R1; ++dy) {
+                        const int z2 = zz + dz, y2 = yy + dy;
+                        if (z2 < bk.z0 || z2 >= zend || y2 < bk.y0 || y2 >= yend) continue;
+                        const int32_t B = at(z2, y2, bk.x0 - 1);
+                        if (B != 0) unite(A, B);
+                    }
+            }
         }
     }
 }
 
 // Every foreground voxel takes 1 + its root's position; four consecutive
-// voxels per thread, and a label equal to the previous voxel's reuses its
-// root.  The merge is over, so every entry read is an ancestor whatever this
-// kernel has already rewritten, and roots are never rewritten.
-__global__ __launch_bounds__(256) void k_zfinal(VolArgs v)
+// voxels per thread, whose first hops are issued together, and a label
+// equal to the previous voxel's reuses its root.  The merge is over, so
+// every entry read is an ancestor whatever this kernel has already
+// rewritten, and roots are never rewritten.
+__global__ __launch_bounds__(256) void k_vfinal(VolArgs v)
 {
     const int64_t n = (int64_t)v.D * v.H * v.W;
     const int64_t q = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
@@ -2075,24 +2276,32 @@ __global__ __launch_bounds__(256) void k_zfinal(VolArgs v)
     } else {
         for (int i = 0; i < 4; ++i) L[i] = q + i < n ? ld_global(v.labels + q + i) : 0;
     }
-    int32_t o[4];
-    int32_t lastL = 0, lastR = 0;
-    bool changed = false;
+    uint32_t r[4], p[4];
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
-        o[i] = L[i];
-        if (L[i] == 0) continue;
-        if (L[i] != lastL) {
-            uint32_t r = (uint32_t)L[i] - 1u;
-            if ((int64_t)r >= n) continue;
-            while (true) {
-                const uint32_t p = (uint32_t)ld_global(v.labels + r) - 1u;
-                if (p == r || (int64_t)p >= n) break;
-                r = p;
-            }
-            lastL = L[i];
-            lastR = (int32_t)(r + 1u);
+        r[i] = (uint32_t)L[i] - 1u;
+        p[i] = r[i];
+        const bool fresh = L[i] != 0 && (i == 0 || L[i] != L[i - 1]) && (int64_t)r[i] < n;
+        if (fresh) p[i] = (uint32_t)ld_global(v.labels + r[i]) - 1u;
+    }
+    int32_t o[4];
+    bool changed = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (L[i] == 0 || (int64_t)r[i] >= n) {
+            o[i] = L[i];
+            continue;
         }
-        o[i] = lastR;
+        if (i > 0 && L[i] == L[i - 1]) {
+            o[i] = o[i - 1];
+        } else {
+            uint32_t a = r[i], b = p[i];
+            while (b != a && (int64_t)b < n) {
+                a = b;
+                b = (uint32_t)ld_global(v.labels + a) - 1u;
+            }
+            o[i] = (int32_t)(a + 1u);
+        }
         changed |= o[i] != L[i];
     }
     if (!changed) return;
@@ -2316,18 +2525,21 @@ hipError_t launch_ablation(const BatchArgs& b, const Workspace& ws, hipStream_t 
 
 hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st, KernelTimer* timer)
 {
-    const int64_t S = (int64_t)v.H * v.W, n = (int64_t)v.D * S;
+    const int64_t n = (int64_t)v.D * v.H * v.W;
     if (n == 0) return hipSuccess;
-    if (v.D > 1) {
-        const int nbx = (v.W + ZB_W - 1) / ZB_W, nby = (v.H + ZB_H - 1) / ZB_H;
-        const unsigned g = (unsigned)((int64_t)(v.D - 1) * nbx * nby);
-        timer_begin(timer, KIND_ZMERGE, st);
-        if (conn == 26) k_zmerge<26><<<g, 256, 0, st>>>(v, nbx, nby);
-        else k_zmerge<6><<<g, 256, 0, st>>>(v, nbx, nby);
-        timer_end(timer, KIND_ZMERGE, st);
-        timer_begin(timer, KIND_ZFINAL, st);
-        k_zfinal<<<(unsigned)((n / 4 + 256) / 256), 256, 0, st>>>(v);
-        timer_end(timer, KIND_ZFINAL, st);
+    const unsigned g = (unsigned)((int64_t)v.nbx * v.nby * v.nbz);
+    timer_begin(timer, KIND_VLOCAL, st);
+    if (conn == 26) k_vlocal<26><<<g, VNT, 0, st>>>(v);
+    else k_vlocal<6><<<g, VNT, 0, st>>>(v);
+    timer_end(timer, KIND_VLOCAL, st);
+    if (g > 1) {  // one brick: its components are the volume's, labels final
+        timer_begin(timer, KIND_VMERGE, st);
+        if (conn == 26) k_vmerge<26><<<g, VNT, 0, st>>>(v);
+        else k_vmerge<6><<<g, VNT, 0, st>>>(v);
+        timer_end(timer, KIND_VMERGE, st);
+        timer_begin(timer, KIND_VFINAL, st);
+        k_vfinal<<<(unsigned)((n / 4 + 256) / 256), 256, 0, st>>>(v);
+        timer_end(timer, KIND_VFINAL, st);
     }
     return hipGetLastError();
 }

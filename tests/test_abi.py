@@ -118,7 +118,8 @@ def test_ablation_validation(lib, args, status):
     ((FAKE_IMG, 2, 4, 4, 4, 8, 26, FAKE_OUT), -1),            # slice pitch < slice
     ((FAKE_IMG, 2, 4, 4, 4, 16, 26, FAKE_IMG + 8), -1),       # overlap
     ((FAKE_IMG, 1024, 2048, 2048, 2048, 1 << 22, 26, FAKE_OUT), -2),  # > 2^31 voxels
-    ((FAKE_IMG, 9_000_000, 1, 1, 1, 1, 6, FAKE_OUT), -2),     # one tile per 1x1 slice: too many
+    ((FAKE_IMG, 65536, 32768, 1, 1, 32768, 6, FAKE_OUT), -2),  # 2^31 voxels exactly
+    ((FAKE_IMG, 2, 4, 4, 4, 16, 0, FAKE_OUT), -1),            # connectivity 0
     ((FAKE_IMG, 0, 4, 4, 4, 16, 26, FAKE_OUT), 0),            # empty volume
 ])
 def test_volume_validation(lib, args, status):

@@ -64,7 +64,7 @@ def test_bench_size_128(ccl, conn):
 
 
 def test_repeated_volume_labelling(ccl):
-    # the merge across slices races on the label map; many repetitions
+    # the merge across brick faces races on the label map; many repetitions
     vol = wl.bernoulli3d(64, 96, 96, 0.35, seed=9)
     d = torch.from_numpy(vol).cuda()
     want = {c: oracle_label3d(vol, c) for c in (6, 26)}
@@ -117,3 +117,24 @@ def test_more_slice_labels_than_merge_table(ccl, D):
     vol[D // 2, 5:9, 10:190] = 1  # one slice joins a band of columns in-slice
     check(ccl, vol, 6, "checkerboard columns")
     check(ccl, vol, 26, "checkerboard columns")
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_every_corner_pattern_on_brick_corners(ccl, conn):
+    # Every 2 x 2 x 2 pattern (256 of them) centred on points where eight
+    # bricks meet (bricks are 64 x 8 x 8 voxels along x, y, z), each site
+    # isolated by background; with 26-connectivity the diagonal contacts
+    # cross two or three brick faces at once.  Shifted copies also sit on
+    # points where only two or four bricks meet.
+    D, H, W = 32, 32, 256
+    corners = [(z, y, x) for z in (8, 16, 24) for y in (8, 16, 24) for x in (64, 128, 192)]
+    sites = corners + [(z, y, x + 20) for z, y, x in corners] + \
+        [(z + 4, y, x) for z, y, x in corners]
+    rng = np.random.default_rng(5)
+    pats = rng.permutation(256)
+    for n0 in range(0, 256, len(sites)):
+        vol = np.zeros((D, H, W), np.uint8)
+        for (z, y, x), p in zip(sites, pats[n0:n0 + len(sites)]):
+            bits = [(p >> b) & 1 for b in range(8)]
+            vol[z - 1:z + 1, y - 1:y + 1, x - 1:x + 1] = np.array(bits, np.uint8).reshape(2, 2, 2)
+        check(ccl, vol, conn, f"corner patterns {n0}")
