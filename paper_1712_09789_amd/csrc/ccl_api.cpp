@@ -697,6 +697,9 @@ int ccl_label_3d(const uint8_t* vol, int32_t D, int32_t H, int32_t W, int64_t pi
     v.nby = (H + VOL_BRICK_H - 1) / VOL_BRICK_H;
     v.nbz = (D + VOL_BRICK_D - 1) / VOL_BRICK_D;
     v.vec = ((uintptr_t)labels & 15) == 0;
+    auto magic = [](int64_t d) { return d == 1 ? 0xffffffffu : (uint32_t)((1ull << 32) / (uint64_t)d); };
+    v.wmagic = magic(W);
+    v.smagic = magic((int64_t)H * W);
     hipError_t e = r64::launch_volume(v, connectivity, st, active_timer());
     if (e != hipSuccess) return fail(CCL_ERR_HIP, "%s: launch failed: %s", who, hipGetErrorString(e));
     return CCL_OK;

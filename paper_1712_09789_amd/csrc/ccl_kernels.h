@@ -54,6 +54,7 @@ struct VolArgs {
     int32_t D, H, W;
     int32_t nbx, nby, nbz;  // bricks along x, y, z
     int32_t vec;            // labels is 16-byte aligned
+    uint32_t wmagic, smagic;  // floor(2^32 / W), floor(2^32 / (H * W)); 0xffffffff for 1
 };
 constexpr int VOL_BRICK_W = 64, VOL_BRICK_H = 8, VOL_BRICK_D = 8;  // voxels per brick (x, y, z)
 

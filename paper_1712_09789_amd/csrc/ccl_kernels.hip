@@ -2172,21 +2172,104 @@ __global__ __launch_bounds__(VNT) void k_vlocal(VolArgs v)
 //   x face (x = x0 against x0-1): neighbours in the column to the left
 //       within the brick's own slab and row band (26: z and y +-1).
 // A pair crossing several faces belongs to the first of them in that order.
+// The z and y faces are rows of 64 voxels against rows of the neighbouring
+// plane, staged in LDS: within the brick's 64 columns a stretch of
+// foreground of one row lies in one brick component, so, as in the local
+// step, one union per pair of touching stretches suffices (face neighbours:
+// one per overlapping stretch; with diagonals the 8-connected row edges,
+// plus the two voxels at the ends of the row against the neighbouring
+// bricks' columns x0-1 and x0+64).  The x face is taken voxel by voxel.
 // A thread drops a pair equal to the one it united last, and the workgroup
 // drops pairs another of its threads already holds (LDS hash); labels read
 // may be stale (roots are lowered meanwhile): any ancestor serves.
 constexpr int VM_HASH = 1024;
+constexpr int VM_ROWS = 2 * VB_H + 2 + 2 * VB_D;  // staged rows: zA, zB, yA, yB
+struct VMergeShared {
+    int32_t zA[VB_H][VB_W];          // plane z0, rows y0 .. y0+VB_H-1
+    int32_t zB[VB_H + 2][VB_W + 2];  // plane z0-1, rows y0-1 .. y0+VB_H, columns x0-1 .. x0+64
+    int32_t yA[VB_D][VB_W];          // row y0 of slices z0 .. z0+VB_D-1
+    int32_t yB[VB_D][VB_W + 2];      // row y0-1 of those slices, columns x0-1 .. x0+64
+    uint64_t zAm[VB_H], zBm[VB_H + 2], yAm[VB_D], yBm[VB_D];  // foreground of x0 .. x0+63
+    unsigned long long seen[VM_HASH];
+};
+
 template <int C>
 __global__ __launch_bounds__(VNT) void k_vmerge(VolArgs v)
 {
-    __shared__ unsigned long long seen[VM_HASH];
-    const int tid = threadIdx.x;
-    for (int k = tid; k < VM_HASH; k += VNT) seen[k] = ~0ull;
-    __syncthreads();
+    __shared__ VMergeShared sh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = tid; k < VM_HASH; k += VNT) sh.seen[k] = ~0ull;
     const Brick bk = brick_of(v, blockIdx.x);
     const int64_t S = (int64_t)v.H * v.W;
     const uint32_t n = (uint32_t)((int64_t)v.D * S);
     const int zend = min(bk.z0 + VB_D, v.D), yend = min(bk.y0 + VB_H, v.H);
+    // staged row q: 0 .. 7 zA, 8 .. 17 zB, 18 .. 25 yA, 26 .. 33 yB
+    auto row_of = [&](int q, int& z, int& y) {
+        if (q < VB_H) { z = bk.z0; y = bk.y0 + q; return bk.z0 > 0 && y < v.H; }
+        q -= VB_H;
+        if (q < VB_H + 2) {
+            z = bk.z0 - 1;
+            y = bk.y0 - 1 + q;
+            return bk.z0 > 0 && y >= 0 && y < v.H && (C == 26 || (q > 0 && q <= VB_H));
+        }
+        q -= VB_H + 2;
+        if (q < VB_D) { z = bk.z0 + q; y = bk.y0; return bk.y0 > 0 && z < v.D; }
+        q -= VB_D;
+        z = bk.z0 + q;
+        y = bk.y0 - 1;
+        return bk.y0 > 0 && z < v.D;
+    };
+    constexpr int RPW = (VM_ROWS + 3) / 4;  // staged rows per wavefront
+    int32_t val[RPW];
+    const int xl = bk.x0 + lane;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        int z, y;
+        const int q = wave + 4 * i;
+        val[i] = 0;
+        if (q < VM_ROWS && row_of(q, z, y) && xl < v.W)
+            val[i] = ld_global(v.labels + (int64_t)z * S + (int64_t)y * v.W + xl);
+    }
+    // rim columns x0-1 and x0+64 of the zB and yB rows (26 only)
+    int32_t rim = 0;
+    if (C == 26 && tid < 2 * (VB_H + 2 + VB_D)) {
+        int z, y;
+        const int q = tid >> 1, side = tid & 1;
+        const int qq = q < VB_H + 2 ? VB_H + q : VB_H + (VB_H + 2) + VB_D + (q - (VB_H + 2));
+        const int xr = side ? bk.x0 + VB_W : bk.x0 - 1;
+        if (row_of(qq, z, y) && xr >= 0 && xr < v.W)
+            rim = ld_global(v.labels + (int64_t)z * S + (int64_t)y * v.W + xr);
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int q = wave + 4 * i;
+        if (q >= VM_ROWS) continue;  // wave-uniform
+        const uint64_t m = __ballot(val[i] != 0);
+        if (q < VB_H) {
+            sh.zA[q][lane] = val[i];
+            if (lane == 0) sh.zAm[q] = m;
+        } else if (q < 2 * VB_H + 2) {
+            sh.zB[q - VB_H][lane + 1] = val[i];
+            if (lane == 0) sh.zBm[q - VB_H] = m;
+        } else if (q < 2 * VB_H + 2 + VB_D) {
+            sh.yA[q - (2 * VB_H + 2)][lane] = val[i];
+            if (lane == 0) sh.yAm[q - (2 * VB_H + 2)] = m;
+        } else {
+            sh.yB[q - (2 * VB_H + 2 + VB_D)][lane + 1] = val[i];
+            if (lane == 0) sh.yBm[q - (2 * VB_H + 2 + VB_D)] = m;
+        }
+    }
+    if (C == 26 && tid < 2 * (VB_H + 2 + VB_D)) {
+        const int q = tid >> 1, col = (tid & 1) ? VB_W + 1 : 0;
+        if (q < VB_H + 2) sh.zB[q][col] = rim;
+        else sh.yB[q - (VB_H + 2)][col] = rim;
+    }
+    if (C == 6) {  // columns x0-1 and x0+64 are never read, but keep them defined
+        if (tid < VB_H + 2) sh.zB[tid][0] = sh.zB[tid][VB_W + 1] = 0;
+        if (tid < VB_D) sh.yB[tid][0] = sh.yB[tid][VB_W + 1] = 0;
+    }
+    __syncthreads();
+
     uint32_t la = ~0u, lb = ~0u;  // the pair this thread united last
     auto unite = [&](int32_t A, int32_t B) {
         const uint32_t a = (uint32_t)A - 1u, b = (uint32_t)B - 1u;
@@ -2196,61 +2279,64 @@ __global__ __launch_bounds__(VNT) void k_vmerge(VolArgs v)
         const unsigned long long key = ((unsigned long long)a << 32) | b;
         uint32_t h = (a * 0x9e3779b1u) ^ (b * 0x85ebca77u);
         for (int probe = 0; probe < 8; ++probe, ++h) {
-            const unsigned long long old = atomicCAS(seen + (h & (VM_HASH - 1)), ~0ull, key);
+            const unsigned long long old = atomicCAS(sh.seen + (h & (VM_HASH - 1)), ~0ull, key);
             if (old == key) return;   // another thread of the workgroup unites this pair
             if (old == ~0ull) break;  // claimed a fresh entry
         }
         v_union(v.labels, a, b, n);
     };
-    auto at = [&](int zz, int yy, int xx) {
-        return ld_global(v.labels + (int64_t)zz * S + (int64_t)yy * v.W + xx);
+    // row A (columns x0 .. x0+63) against row B (B[0] = column x0-1), the
+    // edges whose index lies in the window of WW columns from c0
+    constexpr int NB = C == 26 ? 3 : 1;        // neighbouring rows per face row
+    constexpr int WW = C == 26 ? 16 : 8;       // so that the row pairs fill 192 threads
+    constexpr int TPR = VB_W / WW;             // threads per row pair
+    constexpr uint32_t WMASK = (1u << WW) - 1u;
+    static_assert((VB_H + VB_D) * NB * TPR <= VNT - VB_H * VB_D, "row pairs, then the x face");
+    auto rows = [&](const int32_t* A, uint64_t TA, const int32_t* B, uint64_t TB, int c0) {
+        if (C == 6) {
+            const uint64_t o = TA & TB;
+            for (uint32_t e = (uint32_t)((o & ~(o << 1)) >> c0) & WMASK; e; e &= e - 1u) {
+                const int i = __builtin_ctz(e) + c0;
+                unite(A[i], B[i + 1]);
+            }
+            return;
+        }
+        const uint64_t e0 = TA & TB & ~(TA << 1) & ~(TB << 1);
+        const uint64_t e1 = (TA << 1) & TB & ~(TB << 1);  // A at i-1, B at i
+        const uint64_t e2 = TA & (TB << 1) & ~(TA << 1);  // A at i, B at i-1
+        for (uint32_t e = (uint32_t)((e0 | e1 | e2) >> c0) & WMASK; e; e &= e - 1u) {
+            const int i = __builtin_ctz(e) + c0;
+            const int xa = ((e1 >> i) & 1ull) ? i - 1 : i, xb = ((e2 >> i) & 1ull) ? i - 1 : i;
+            unite(A[xa], B[xb + 1]);
+        }
+        if (c0 == 0 && (TA & 1ull) && B[0] != 0) unite(A[0], B[0]);
+        if (c0 == VB_W - WW && (TA >> 63) && B[VB_W + 1] != 0) unite(A[VB_W - 1], B[VB_W + 1]);
     };
-    constexpr int R1 = C == 26 ? 1 : 0;  // neighbourhood radius along the other axes
-    // z face: 64 x VB_H voxels, two per thread
-    if (bk.z0 > 0) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int i = tid + k * VNT, xx = bk.x0 + i % VB_W, yy = bk.y0 + i / VB_W;
-            if (xx >= v.W || yy >= v.H) continue;
-            const int32_t A = at(bk.z0, yy, xx);
-            if (A == 0) continue;
-            for (int dy = -R1; dy <= R1; ++dy)
-                for (int dx = -R1; dx <= R1; ++dx) {
-                    const int y2 = yy + dy, x2 = xx + dx;
-                    if (y2 < 0 || y2 >= v.H || x2 < 0 || x2 >= v.W) continue;
-                    const int32_t B = at(bk.z0 - 1, y2, x2);
-                    if (B != 0) unite(A, B);
-                }
+    const int task = tid / TPR, c0 = (tid % TPR) * WW;
+    if (task < VB_H * NB) {  // z face
+        if (bk.z0 > 0) {
+            const int k = task / NB, j = k + 1 + (C == 26 ? task % NB - 1 : 0);
+            rows(sh.zA[k], sh.zAm[k], sh.zB[j], sh.zBm[j], c0);
         }
+    } else if (task < (VB_H + VB_D) * NB) {  // y face
+        const int t2 = task - VB_H * NB, k = t2 / NB, k2 = k + (C == 26 ? t2 % NB - 1 : 0);
+        if (bk.y0 > 0 && k2 >= 0 && k2 < VB_D && bk.z0 + k2 < zend)
+            rows(sh.yA[k], sh.yAm[k], sh.yB[k2], sh.yBm[k2], c0);
     }
-    // y face: 64 x VB_D voxels, two per thread
-    if (bk.y0 > 0) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int i = tid + k * VNT, xx = bk.x0 + i % VB_W, zz = bk.z0 + i / VB_W;
-            if (xx >= v.W || zz >= zend) continue;
-            const int32_t A = at(zz, bk.y0, xx);
-            if (A == 0) continue;
-            for (int dz = -R1; dz <= R1; ++dz)
-                for (int dx = -R1; dx <= R1; ++dx) {
-                    const int z2 = zz + dz, x2 = xx + dx;
-                    if (z2 < bk.z0 || z2 >= zend || x2 < 0 || x2 >= v.W) continue;
-                    const int32_t B = at(z2, bk.y0 - 1, x2);
-                    if (B != 0) unite(A, B);
-                }
-        }
-    }
-    // x face: VB_H x VB_D voxels, one per thread of the first quarter
-    if (bk.x0 > 0 && tid < VB_H * VB_D) {
-        const int yy = bk.y0 + tid % VB_H, zz = bk.z0 + tid / VB_H;
+    // x face: VB_H x VB_D voxels, one per thread of the last quarter
+    constexpr int R1 = C == 26 ? 1 : 0;
+    const int xt = tid - (VNT - VB_H * VB_D);
+    if (bk.x0 > 0 && xt >= 0) {
+        const int yy = bk.y0 + xt % VB_H, zz = bk.z0 + xt / VB_H;
         if (yy < yend && zz < zend) {
-            const int32_t A = at(zz, yy, bk.x0);
+            const int32_t A = ld_global(v.labels + (int64_t)zz * S + (int64_t)yy * v.W + bk.x0);
             if (A != 0) {
                 for (int dz = -R1; dz <= R1; ++dz)
                     for (int dy = -R1; dy <= R1; ++dy) {
                         const int z2 = zz + dz, y2 = yy + dy;
                         if (z2 < bk.z0 || z2 >= zend || y2 < bk.y0 || y2 >= yend) continue;
-                        const int32_t B = at(z2, y2, bk.x0 - 1);
+                        const int32_t B =
+                            ld_global(v.labels + (int64_t)z2 * S + (int64_t)y2 * v.W + bk.x0 - 1);
                         if (B != 0) unite(A, B);
                     }
             }
@@ -2258,58 +2344,88 @@ __global__ __launch_bounds__(VNT) void k_vmerge(VolArgs v)
     }
 }
 
-// Every foreground voxel takes 1 + its root's position; four consecutive
-// voxels per thread, whose first hops are issued together, and a label
-// equal to the previous voxel's reuses its root.  The merge is over, so
-// every entry read is an ancestor whatever this kernel has already
-// rewritten, and roots are never rewritten.
-__global__ __launch_bounds__(256) void k_vfinal(VolArgs v)
+// k_vfinal: one workgroup per brick; every foreground voxel takes 1 + its
+// root's position.  The brick's labels are staged in LDS (each wavefront
+// load and store covers four whole brick rows: row w * 16 + 4q + lane / 16,
+// columns 4 * (lane % 16) .. +3).  A voxel's label names the first voxel
+// of its brick component, which lies in the brick unless the voxel is that
+// first voxel and the merge linked it, so the first hop is mostly an LDS
+// read; only components the merge linked (their first voxel's entry no
+// longer names itself) are chased in the label map.  A label equal to the
+// thread's previous one reuses its root.  The merge is over, so every entry
+// read is an ancestor whatever this kernel has already rewritten, and roots
+// are never rewritten.
+__global__ __launch_bounds__(VNT) void k_vfinal(VolArgs v)
 {
-    const int64_t n = (int64_t)v.D * v.H * v.W;
-    const int64_t q = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (q >= n) return;
-    const bool whole = v.vec && q + 4 <= n;
-    int32_t L[4];
-    if (whole) {
-        const uint4 w = ld_global16(v.labels + q);
-        L[0] = (int32_t)w.x; L[1] = (int32_t)w.y; L[2] = (int32_t)w.z; L[3] = (int32_t)w.w;
-    } else {
-        for (int i = 0; i < 4; ++i) L[i] = q + i < n ? ld_global(v.labels + q + i) : 0;
-    }
-    uint32_t r[4], p[4];
+    __shared__ int32_t Lb[VB_ROWS][VB_W];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Brick bk = brick_of(v, blockIdx.x);
+    const int64_t S = (int64_t)v.H * v.W;
+    const uint32_t n = (uint32_t)((int64_t)v.D * S);
+    const int xw = 4 * (lane % 16);
+    int32_t in[4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        r[i] = (uint32_t)L[i] - 1u;
-        p[i] = r[i];
-        const bool fresh = L[i] != 0 && (i == 0 || L[i] != L[i - 1]) && (int64_t)r[i] < n;
-        if (fresh) p[i] = (uint32_t)ld_global(v.labels + r[i]) - 1u;
-    }
-    int32_t o[4];
-    bool changed = false;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (L[i] == 0 || (int64_t)r[i] >= n) {
-            o[i] = L[i];
-            continue;
-        }
-        if (i > 0 && L[i] == L[i - 1]) {
-            o[i] = o[i - 1];
+    for (int q = 0; q < 4; ++q) {
+        const int rr = wave * 16 + 4 * q + lane / 16;
+        const int yy = bk.y0 + rr % VB_H, zz = bk.z0 + rr / VB_H, xx = bk.x0 + xw;
+        in[q][0] = in[q][1] = in[q][2] = in[q][3] = 0;
+        if (zz >= v.D || yy >= v.H || xx >= v.W) continue;
+        const int32_t* src = v.labels + (int64_t)zz * S + (int64_t)yy * v.W + xx;
+        if (v.W - xx >= 4 && v.vec && (((uintptr_t)src & 15u) == 0)) {
+            const uint4 w = ld_global16(src);
+            in[q][0] = (int32_t)w.x; in[q][1] = (int32_t)w.y;
+            in[q][2] = (int32_t)w.z; in[q][3] = (int32_t)w.w;
         } else {
-            uint32_t a = r[i], b = p[i];
-            while (b != a && (int64_t)b < n) {
-                a = b;
-                b = (uint32_t)ld_global(v.labels + a) - 1u;
-            }
-            o[i] = (int32_t)(a + 1u);
+            for (int j = 0; j < 4; ++j)
+                if (xx + j < v.W) in[q][j] = ld_global(src + j);
         }
-        changed |= o[i] != L[i];
     }
-    if (!changed) return;
-    if (whole) {
-        st_global16(v.labels + q, o[0], o[1], o[2], o[3]);
-    } else {
-        for (int i = 0; i < 4; ++i)
-            if (q + i < n && o[i] != L[i]) st_global(v.labels + q + i, o[i]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rr = wave * 16 + 4 * q + lane / 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Lb[rr][xw + j] = in[q][j];
+    }
+    __syncthreads();
+    int32_t lastL = 0, lastR = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rr = wave * 16 + 4 * q + lane / 16;
+        const int yy = bk.y0 + rr % VB_H, zz = bk.z0 + rr / VB_H, xx = bk.x0 + xw;
+        if (zz >= v.D || yy >= v.H || xx >= v.W) continue;
+        int32_t o[4];
+        bool changed = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t L = in[q][j];
+            o[j] = L;
+            if (L == 0 || (uint32_t)L - 1u >= n) continue;
+            if (L != lastL) {
+                uint32_t p = (uint32_t)L - 1u, zp, rem, yp, xp;
+                divmod_w(p, (uint32_t)S, v.smagic, zp, rem);
+                divmod_w(rem, (uint32_t)v.W, v.wmagic, yp, xp);
+                const int kz = (int)zp - bk.z0, ky = (int)yp - bk.y0, kx = (int)xp - bk.x0;
+                const bool here = kz >= 0 && kz < VB_D && ky >= 0 && ky < VB_H && kx >= 0 &&
+                                  kx < VB_W;
+                uint32_t e = (uint32_t)(here ? Lb[kz * VB_H + ky][kx] : ld_global(v.labels + p)) - 1u;
+                while (e != p && e < n) {
+                    p = e;
+                    e = (uint32_t)ld_global(v.labels + p) - 1u;
+                }
+                lastL = L;
+                lastR = (int32_t)(p + 1u);
+            }
+            o[j] = lastR;
+            changed |= o[j] != L;
+        }
+        if (!changed) continue;
+        int32_t* dst = v.labels + (int64_t)zz * S + (int64_t)yy * v.W + xx;
+        if (v.W - xx >= 4 && v.vec && (((uintptr_t)dst & 15u) == 0)) {
+            st_global16(dst, o[0], o[1], o[2], o[3]);
+        } else {
+            for (int j = 0; j < 4; ++j)
+                if (xx + j < v.W && o[j] != in[q][j]) st_global(dst + j, o[j]);
+        }
     }
 }
 
@@ -2538,7 +2654,7 @@ hipError_t launch_volume(const VolArgs& v, int conn, hipStream_t st, KernelTimer
         else k_vmerge<6><<<g, VNT, 0, st>>>(v);
         timer_end(timer, KIND_VMERGE, st);
         timer_begin(timer, KIND_VFINAL, st);
-        k_vfinal<<<(unsigned)((n / 4 + 256) / 256), 256, 0, st>>>(v);
+        k_vfinal<<<g, VNT, 0, st>>>(v);
         timer_end(timer, KIND_VFINAL, st);
     }
     return hipGetLastError();
