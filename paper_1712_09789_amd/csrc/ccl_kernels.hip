@@ -2019,10 +2019,9 @@ __device__ __forceinline__ uint32_t vrun(const VolLocalShared& sh, int r, int x)
 // where nr does not continue from i-1, (i, i-1) where r does not (at most
 // one per column; for two touching runs, the edge at the larger of their
 // first columns is listed).
-// With `last` (the slice below, whose runs already point at roots of the
-// brick's slices), an edge is dropped when the two runs' current parents are
-// the pair this thread united last: the runs of the slice below that one
-// run touches mostly belong to one slice component.
+// With `last`, an edge is dropped when the two runs' current parents are
+// the pair this thread united last (after the unification most runs point at
+// their root, and the runs one run touches mostly share one).
 template <bool DIAG>
 __device__ __forceinline__ void vlink_rows(VolLocalShared& sh, int r, int nr, int c0,
                                            uint32_t* last = nullptr)
@@ -2104,23 +2103,51 @@ __global__ __launch_bounds__(VNT) void k_vlocal(VolArgs v)
             sh.P[id] = pk((uint32_t)(r * VB_W + __builtin_ctz(w) + c0), id);
     }
     __syncthreads();
-    // in-slice edges first, then every run points at its slice root, so
-    // that the edges to the slice below can be deduplicated on roots
-    if (ky > 0) vlink_rows<C == 26>(sh, r, r - 1, c0);
+    // Coarse links (Section 3.1.2, column connection lifted to 3-D): every
+    // run takes the entry of a run it touches in the first of its earlier
+    // neighbour rows that has one (the row above, then the rows of the slice
+    // below), a plain store since each run has one writer.  The entry read is
+    // that run's label or an ancestor with a smaller key.
+    {
+        const uint64_t st = sh.S[r], m = sh.M[r];
+        uint32_t id = sh.base[r] + popc64(st & ~(~0ull << c0));
+        for (uint32_t w = (uint32_t)(st >> c0) & 0xffffu; w; w &= w - 1u, ++id) {
+            const int s0 = __builtin_ctz(w) + c0;
+            const int e = s0 + ctz64_or64(~(m >> s0)) - 1;
+            const uint64_t span = C == 26 ? span_mask(s0 > 0 ? s0 - 1 : 0, e < 63 ? e + 1 : 63)
+                                          : span_mask(s0, e);
+            int nr = -1;
+            uint64_t t = 0;
+            if (ky > 0 && (t = sh.M[r - 1] & span)) nr = r - 1;
+            else if (kz > 0) {
+                if (C == 26 && ky > 0 && (t = sh.M[r - VB_H - 1] & span)) nr = r - VB_H - 1;
+                else if ((t = sh.M[r - VB_H] & span)) nr = r - VB_H;
+                else if (C == 26 && ky < VB_H - 1 && (t = sh.M[r - VB_H + 1] & span))
+                    nr = r - VB_H + 1;
+            }
+            if (nr >= 0) lds_st(sh.P + id, lds_ld(sh.P + vrun(sh, nr, ctz64(t))));
+        }
+    }
     __syncthreads();
+    // Unification: every run points at its coarse root, then the edges to
+    // the earlier rows are merged (Section 3.1.3); an edge whose two runs'
+    // current parents are the pair this thread merged last is dropped.
     const uint32_t R = sh.base[VB_ROWS];
     for (uint32_t id = tid; id < R; id += VNT)
         __hip_atomic_fetch_min(sh.P + id, pfind(sh.P, id), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
-    if (kz > 0) {
+    {
         uint32_t last = ~0u;
-        if (C == 6) {
-            vlink_rows<false>(sh, r, r - VB_H, c0, &last);
-        } else {
-            if (ky > 0) vlink_rows<true>(sh, r, r - VB_H - 1, c0, &last);
-            vlink_rows<true>(sh, r, r - VB_H, c0, &last);
-            if (ky < VB_H - 1) vlink_rows<true>(sh, r, r - VB_H + 1, c0, &last);
+        if (ky > 0) vlink_rows<C == 26>(sh, r, r - 1, c0, &last);
+        if (kz > 0) {
+            if (C == 6) {
+                vlink_rows<false>(sh, r, r - VB_H, c0, &last);
+            } else {
+                if (ky > 0) vlink_rows<true>(sh, r, r - VB_H - 1, c0, &last);
+                vlink_rows<true>(sh, r, r - VB_H, c0, &last);
+                if (ky < VB_H - 1) vlink_rows<true>(sh, r, r - VB_H + 1, c0, &last);
+            }
         }
     }
     __syncthreads();
