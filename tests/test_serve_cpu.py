@@ -300,3 +300,22 @@ def test_stall_is_reported_not_spun():
     with pytest.raises(RuntimeError, match="admission stalled"):
         sched.run(make_requests(10, seed=10, sizes=((32, 32),)))
     assert len(sched.done) == 3
+
+
+def test_collector_paused_while_serving_and_restored():
+    """The cyclic garbage collector is off while run() serves (its full
+    passes stalled the loop) and back on afterwards, also when run() raises."""
+    import gc
+    assert gc.isenabled()
+    clock = VirtualClock()
+    ex = FakeExecutor(clock, budget=10**9)
+    sched = Scheduler(ex, slots=2, max_batch=4, clock=clock)
+    seen = []
+    sched.run(make_requests(12, seed=3), on_step=lambda s: seen.append(gc.isenabled()))
+    assert seen and not any(seen)
+    assert gc.isenabled()
+    ex = FakeExecutor(clock, budget=3 * 32 * 32 * 4)
+    sched = Scheduler(ex, slots=2, clock=clock)
+    with pytest.raises(RuntimeError, match="admission stalled"):
+        sched.run(make_requests(10, seed=10, sizes=((32, 32),)))
+    assert gc.isenabled()
