@@ -77,10 +77,11 @@ def test_repeated_volume_labelling(ccl):
 
 
 def _edge_patterns():
-    """Volumes whose slice-to-slice contacts sit on the 64 x 16 blocks' edges
-    and rims: diagonal lines of single voxels (26-connected only) crossing
-    columns 63/64 and rows 15/16, rows that alternate between y = 15 and 16
-    from slice to slice, and columns that alternate between x = 63 and 64."""
+    """Volumes whose contacts sit on brick faces (bricks are 64 x 8 x 8 voxels
+    along x, y, z): diagonal lines of single voxels (26-connected only)
+    crossing columns 63/64, rows 15/16 and slices 7/8, rows that alternate
+    between y = 15 and 16 from slice to slice, and columns that alternate
+    between x = 63 and 64."""
     D, H, W = 24, 40, 200
     diag = np.zeros((D, H, W), np.uint8)
     for z in range(D):
@@ -105,12 +106,11 @@ def test_block_edge_contacts(ccl, name, conn):
 
 
 @pytest.mark.parametrize("D", [6, 16])
-def test_more_slice_labels_than_merge_table(ccl, D):
+def test_most_runs_and_face_contacts(ccl, D):
     # A 2-D checkerboard repeated on every slice: under 6-connectivity every
-    # foreground voxel is its own slice component and touches the voxel of
-    # the next slice, so every block of a slice pair holds the most distinct
-    # slice labels a block can (one per voxel of half its columns), and the
-    # merge across slices unites 512 pairs per 64 x 16 block.
+    # foreground voxel is its own run, joined only to the voxels of the
+    # slices above and below, so a brick holds the most runs it can (32 per
+    # row) and every foreground voxel of a z face is a contact of its own.
     H, W = 48, 200
     y, x = np.mgrid[0:H, 0:W]
     vol = np.broadcast_to(((x + y) % 2 == 0).astype(np.uint8), (D, H, W)).copy()
