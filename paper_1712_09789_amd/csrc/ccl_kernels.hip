@@ -1653,13 +1653,26 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
     if (tid == 0) overflow = 0;
     __syncthreads();
     const int I = (int)(blockIdx.x % (unsigned)outx), J = (int)(blockIdx.x / (unsigned)outx);
-    for (int part = 0; part < MERGE_FAN * MERGE_FAN; ++part) {
-        const int i = I * MERGE_FAN + part % MERGE_FAN, j = J * MERGE_FAN + part / MERGE_FAN;
-        if (i >= inx || j >= iny) continue;
-        const int64_t sg = (int64_t)j * inx + i;
-        const uint32_t n = in_cnt[sg];
-        for (uint32_t k = tid; k < n; k += MERGE_T) {
-            const StatRec r = in[sg * in_cap + k];
+    // one wavefront per tile of the region: every tile's count and records
+    // are loaded at once (one round trip each, not one per tile in turn)
+    constexpr int PARTS = MERGE_FAN * MERGE_FAN, TPP = MERGE_T / PARTS;  // threads per tile
+    static_assert(MERGE_T % PARTS == 0 && TPP == 64, "a wavefront per tile");
+    const int part = tid / TPP, pl = tid % TPP;
+    const int i = I * MERGE_FAN + part % MERGE_FAN, j = J * MERGE_FAN + part / MERGE_FAN;
+    const int64_t sg = (int64_t)j * inx + i;
+    const uint32_t n = (i < inx && j < iny) ? ld_global(in_cnt + sg) : 0u;
+    constexpr int RPT = 4;  // records loaded together per thread
+    for (uint32_t k0 = 0; k0 < n; k0 += RPT * TPP) {
+        StatRec rec[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const uint32_t k = k0 + pl + q * TPP;
+            if (k < n) rec[q] = ld_global(in + sg * in_cap + k);
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            if (k0 + pl + q * TPP >= n) continue;
+            const StatRec& r = rec[q];
             uint32_t h = ((uint32_t)r.num * 0x9E3779B1u) >> (32 - 11);
             static_assert(MERGE_HT == 1 << 11, "hash width");
             bool placed = false;
