@@ -1483,14 +1483,16 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
         sh.sums[tid] = sh.cols[tid] = sh.rows[tid] = 0ull;
         sh.lab[tid] = st.fin[T * NSLOTS + tid];  // used at representative slots only
     }
+    // the whole run table, in the same round trip as the loads above (its
+    // entries past the tile's run count are never read)
+    static_assert(RUNTAB_PER_TILE % 8 == 0 && RUNTAB_PER_TILE / 8 <= ST, "one chunk per thread");
+    if (tid < RUNTAB_PER_TILE / 8)
+        reinterpret_cast<uint4*>(sh.ent)[tid] = ld_global16(ws.runtab + T * RUNTAB_PER_TILE + 8 * tid);
     if (tid == 0) sh.nrec = 0u;
     __syncthreads();
     build_lines<D>(sh, tid);
     if (tid < NT) list_runs<D>(sh, sh.RL, tid);
     const uint32_t R = sh.base[Geo<D>::NL];
-    if (tid < NT && 8u * tid < R)
-        reinterpret_cast<uint4*>(sh.ent)[tid] =
-            reinterpret_cast<const uint4*>(ws.runtab + T * RUNTAB_PER_TILE)[tid];
     for (uint32_t id = tid; id < R; id += ST) {
         sh.isums[id] = sh.icols[id] = sh.irows[id] = 0ull;
         sh.iroot[id] = 0;
