@@ -63,6 +63,15 @@ def test_bench_size_128(ccl, conn):
         check(ccl, wl.make3d(kind, 128, 128, 128, seed=0, **kw), conn, f"128^3 {kind}{kw}")
 
 
+@pytest.mark.parametrize("conn", [6, 26])
+def test_bench_size_512(ccl, conn):
+    # the benchmark's 512^3 Bernoulli volumes (p = 0.3 near the 6-connected
+    # percolation threshold, p = 0.5 one spanning component), every voxel
+    # against the oracle
+    for p in (0.3, 0.5):
+        check(ccl, wl.make3d("bernoulli", 512, 512, 512, seed=0, p=p), conn, f"512^3 p={p}")
+
+
 def test_repeated_volume_labelling(ccl):
     # the merge across brick faces races on the label map; many repetitions
     vol = wl.bernoulli3d(64, 96, 96, 0.35, seed=9)
