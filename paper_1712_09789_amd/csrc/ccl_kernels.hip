@@ -268,26 +268,26 @@ __device__ __forceinline__ uint64_t g_hop(const uint64_t* p, int step)
     return step < 2 ? ld_global(p) : g_ld(p);
 }
 
-// Root of n, given v = F[n] already loaded.  A walk of more than one hop
-// then points n straight at the root it found, with one atomic min (so a
-// concurrent link of n to a smaller key is never undone); the nodes passed
-// are left alone.  Halving every second hop instead made the merge across
-// groups slower where one component crosses the seams many times (8192^2
-// spiral 111 -> 70 us, serpentine 158 -> 112 us without it): those atomics
-// all land on the few nodes every chain passes through.
+// Root of n, given v = F[n] already loaded.  Halves the path on the way
+// with plain stores: a node is rewritten only after it was read as a
+// non-root (roots are never stored to, and a node that has a parent never
+// becomes a root again), and only with an ancestor, whose key is smaller.
+// Such a store may replace a link another thread made meanwhile with its
+// atomic min; that thread found the node no longer a root (the min returned
+// another parent) and goes on uniting from that parent, so the link it made
+// is not needed.  Atomic mins for the halving made the merge across groups
+// slower where one component crosses the seams many times (all chains pass
+// the same few nodes); plain stores gained on those images (8192^2
+// serpentine 135 -> 111 us) and cost nothing elsewhere.
 __device__ Root g_find_from(uint64_t* F, uint32_t n, uint64_t v)
 {
-    const uint32_t n0 = n;
     for (int step = 0;; step += 2) {
         uint32_t p = (uint32_t)v;
         if (p == n) return Root{n, (uint32_t)(v >> 32)};
         uint64_t vp = g_hop(F + p, step);
         uint32_t pp = (uint32_t)vp;
-        if (pp == p) {
-            if (step > 0)
-                __hip_atomic_fetch_min(F + n0, vp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return Root{p, (uint32_t)(vp >> 32)};
-        }
+        if (pp == p) return Root{p, (uint32_t)(vp >> 32)};
+        st_global(F + n, vp);
         n = pp;
         v = g_hop(F + n, step + 1);
     }
