@@ -1966,14 +1966,14 @@ __device__ __forceinline__ uint32_t vl_hop(const int32_t* p, int step)
 }
 
 // Root of r, given its parent p and grandparent pp (p not a root, pp != p):
-// halves the path on the way.  Entries always name smaller positions, so a
-// chase ends at a root; the bound check only keeps a corrupted entry from
-// reading outside the map.
+// halves the path on the way, with plain stores of ancestors into entries
+// read as non-roots (safe for the reasons given at g_find_from).  Entries
+// always name smaller positions, so a chase ends at a root; the bound check
+// only keeps a corrupted entry from reading outside the map.
 __device__ uint32_t v_find_on(int32_t* lab, uint32_t r, uint32_t p, uint32_t pp, uint32_t n)
 {
     for (int step = 2;; step += 2) {
-        __hip_atomic_fetch_min(lab + r, (int32_t)(pp + 1u), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        st_global(lab + r, (int32_t)(pp + 1u));
         r = pp;
         p = vl_hop(lab + r, step);
         if (p == r || p >= n) return r;
