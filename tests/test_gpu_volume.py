@@ -42,6 +42,17 @@ def test_random_shapes(ccl, shape, p, conn):
 
 
 @pytest.mark.parametrize("conn", [6, 26])
+@pytest.mark.parametrize("shape", [(9, 1, 130), (12, 70, 1), (1, 9, 9), (130, 1, 1), (1, 1, 200),
+                                   (17, 9, 65), (8, 8, 64), (16, 16, 128)])
+def test_thin_and_exact_brick_shapes(ccl, shape, conn):
+    # one-voxel axes (rows of one voxel, single columns, one slice), and
+    # volumes that are whole bricks (64 x 8 x 8 along x, y, z) or one voxel
+    # past them
+    for p in (0.4, 0.8):
+        check(ccl, wl.bernoulli3d(*shape, p, seed=sum(shape) + int(10 * p)), conn, f"bernoulli{p}")
+
+
+@pytest.mark.parametrize("conn", [6, 26])
 @pytest.mark.parametrize("kind,kw", [("blobs", {"sigma": 2.0}), ("blobs", {"sigma": 4.0}),
                                      ("checkerboard", {}), ("full", {}), ("empty", {}),
                                      ("slabs", {}), ("bernoulli", {"p": 0.3})])
