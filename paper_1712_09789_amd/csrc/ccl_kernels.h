@@ -128,7 +128,7 @@ constexpr int SCAN_BLK = 4 * SCAN_T;        // segments per first-level scan blo
 // Partial statistics of one component over part of the image, in global
 // coordinates.
 struct StatRec {
-    int32_t num;  // component number
+    int32_t label;  // the component's label
     int32_t area, x_min, x_max, y_min, y_max;
     int64_t sum_x, sum_y;
 };

@@ -1459,7 +1459,7 @@ __device__ __forceinline__ int64_t tile_number(const SH& sh, int ky, int kx)
 // updated once per tile.  The run holding a border component's smallest
 // pixel writes the entry's starting values (label, top row, empty sums and
 // box).  Components whose smallest pixel lies in this tile are numbered
-// from the tile's staged row counts.
+// from the tile's staged row counts; the partial records carry the label.
 constexpr int ST = 1024;  // k_stats threads per tile (its LDS allows two workgroups per
                           // compute unit, so a wide workgroup keeps the unit busy)
 template <int D>
@@ -1605,10 +1605,9 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
     const uint64_t v = tid < NSLOTS ? sh.sums[tid] : 0ull;
     const int area = (int)(v & 0x1fffu);
     if (area > 0) {
-        const int64_t num = component_number(a, st, sh.lab[tid]);
-        if (num < st.capacity) {
+        {
             StatRec r;
-            r.num = (int32_t)num;
+            r.label = sh.lab[tid];
             r.area = area;
             const uint64_t cm = sh.cols[tid], rm = sh.rows[tid];
             r.x_min = gx0 + ctz64(cm);
@@ -1626,7 +1625,9 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
 
 // Merge of the tiles' partial records: workgroup (I, J) combines the
 // records of tiles (4I .. 4I+3, 4J .. 4J+3) in an LDS hash table keyed by
-// component number.  A combined record whose box stays off the region's
+// label, and numbers each combined record once (the tiles leave their
+// records unnumbered, which spares them a round trip to the scanned counts
+// per tile).  A combined record whose box stays off the region's
 // inner edges (image edges do not count) is the whole component: it cannot
 // reach outside without crossing them, so its fields are stored into the
 // component's entry (started by the tile holding its smallest pixel, which
@@ -1637,9 +1638,10 @@ __global__ __launch_bounds__(ST) void k_stats(BatchArgs b, Workspace ws, StatsWs
 constexpr int MERGE_T = 1024;
 __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatRec* in,
                                                           const uint32_t* in_cnt, int in_cap,
-                                                          int inx, int iny, int outx, int W,
-                                                          int H)
+                                                          int inx, int iny, int outx,
+                                                          ImageArgs a)
 {
+    const int W = a.W, H = a.H;
     __shared__ int32_t hkey[MERGE_HT], harea[MERGE_HT], hxmin[MERGE_HT], hxmax[MERGE_HT],
         hymin[MERGE_HT], hymax[MERGE_HT];
     __shared__ unsigned long long hsx[MERGE_HT], hsy[MERGE_HT];
@@ -1675,12 +1677,12 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
         for (int q = 0; q < RPT; ++q) {
             if (k0 + pl + q * TPP >= n) continue;
             const StatRec& r = rec[q];
-            uint32_t h = ((uint32_t)r.num * 0x9E3779B1u) >> (32 - 11);
+            uint32_t h = ((uint32_t)r.label * 0x9E3779B1u) >> (32 - 11);
             static_assert(MERGE_HT == 1 << 11, "hash width");
             bool placed = false;
             for (int probe = 0; probe < 64 && !placed; ++probe, h = (h + 1u) & (MERGE_HT - 1)) {
-                const int32_t old = atomicCAS(&hkey[h], -1, r.num);
-                if (old == -1 || old == r.num) {
+                const int32_t old = atomicCAS(&hkey[h], -1, r.label);
+                if (old == -1 || old == r.label) {
                     atomicAdd(&harea[h], r.area);
                     atomicMin(&hxmin[h], r.x_min);
                     atomicMax(&hxmax[h], r.x_max);
@@ -1693,8 +1695,10 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
             }
             if (!placed) {
                 overflow = 1;
-                add_stats(st.comps + r.num, r.area, r.x_min, r.x_max, r.y_max,
-                          (uint64_t)r.sum_x, (uint64_t)r.sum_y);
+                const int64_t num = component_number(a, st, r.label);
+                if (num < st.capacity)
+                    add_stats(st.comps + num, r.area, r.x_min, r.x_max, r.y_max,
+                              (uint64_t)r.sum_x, (uint64_t)r.sum_y);
             }
         }
     }
@@ -1705,8 +1709,10 @@ __global__ __launch_bounds__(MERGE_T) void k_stats_merge(StatsWs st, const StatR
     const int x1 = min(x0 + span, W) - 1, y1 = min(y0 + span, H) - 1;
     const bool plain_ok = overflow == 0;
     for (int h = tid; h < MERGE_HT; h += MERGE_T) {
-        const int32_t num = hkey[h];
-        if (num < 0) continue;
+        const int32_t label = hkey[h];
+        if (label < 0) continue;
+        const int64_t num = component_number(a, st, label);
+        if (num >= st.capacity) continue;
         const bool crosses = (hxmin[h] == x0 && x0 > 0) || (hxmax[h] == x1 && x1 < W - 1) ||
                              (hymin[h] == y0 && y0 > 0) || (hymax[h] == y1 && y1 < H - 1);
         CompStats* c = st.comps + num;
@@ -2617,7 +2623,7 @@ static hipError_t launch_all(const BatchArgs& b, const Workspace& ws, hipStream_
         const ImageArgs& a = b.one;
         static_assert(TW == TILE_ROWS, "square tiles: merge regions are squares of tiles");
         k_stats_merge<<<(unsigned)(stats->g1x * stats->g1y), MERGE_T, 0, st>>>(
-            *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, stats->g1x, a.W, a.H);
+            *stats, stats->rec0, stats->cnt0, NSLOTS, a.ntx, a.nty, stats->g1x, a);
     }
     timer_end(timer, KIND_STATS, st);
 #endif
