@@ -211,6 +211,35 @@ def test_random_sweep(ccl):
         assert_parity(ccl, img, conn, f"sweep {trial}")
 
 
+def test_random_sweep_full_size(ccl):
+    """Seeded sweep at full sizes (ragged sides just under 4096 and 8192),
+    where every compute unit holds several workgroups and each workgroup of
+    the persistent local step labels several tiles in turn: random density
+    or blob scale, connectivity and tile height, each image labelled twice
+    (the two results must be equal) and compared with the oracle."""
+    rng = np.random.default_rng(777)
+    for trial in range(12):
+        N = 8192 if trial % 4 == 0 else 4096
+        H, W = N - int(rng.integers(0, 64)), N - int(rng.integers(0, 64))
+        conn = int(rng.choice([4, 8]))
+        rows = int(rng.choice([32, 64, 128]))
+        if trial % 2:
+            img = wl.blobs(H, W, float(rng.choice([2.0, 4.0, 8.0])), seed=trial)
+        else:
+            img = wl.bernoulli(H, W, float(rng.uniform(0.05, 0.95)), seed=trial)
+        print(f"[parity] full-size sweep {trial} {img.shape} conn={conn} rows={rows}", flush=True)
+        d = to_dev(img)
+        a = ccl.label(d, conn, tile_rows=rows)
+        b = ccl.label(d, conn, tile_rows=rows)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), f"sweep {trial}: two labellings differ"
+        got, want = a.cpu().numpy(), oracle_label(img, conn)
+        if not np.array_equal(got, want):
+            y, x = np.argwhere(got != want)[0]
+            raise AssertionError(f"sweep {trial} {img.shape} conn={conn} rows={rows}: "
+                                 f"first mismatch at ({y},{x}) got {got[y, x]} want {want[y, x]}")
+
+
 # --- configs at full size ---------------------------------------------------
 
 @pytest.mark.parametrize("seed", range(5))
