@@ -135,8 +135,8 @@ struct StatRec {
 constexpr int MERGE_FAN = 4;     // a merge workgroup takes the records of 4 x 4 tiles
 constexpr int MERGE_HT = 2048;   // its hash table of distinct components
 
-// Written to the component count by the statistics kernels when a label
-// read back from the label map is impossible for its pixel (see ccl.h).
+// Written to the component count by the statistics kernels when the label
+// a run is given is impossible for its pixel (see ccl.h).
 constexpr int64_t CCL_STATS_INCONSISTENT = -1;
 
 struct StatsWs {
