@@ -2051,7 +2051,10 @@ __device__ __forceinline__ uint32_t vrun(const VolLocalShared& sh, int r, int x)
 // first columns is listed).
 // With `last`, an edge is dropped when the two runs' current parents are
 // the pair this thread united last (after the unification most runs point at
-// their root, and the runs one run touches mostly share one).
+// their root, and the runs one run touches mostly share one), and for face
+// neighbours also when the two runs have the same parent (already one set;
+// 512^3 volumes 1-3 % faster under 6-connectivity, while under 26 the
+// early exit only split the wavefronts: Bernoulli 0.5 656 -> 694 us).
 template <bool DIAG>
 __device__ __forceinline__ void vlink_rows(VolLocalShared& sh, int r, int nr, int c0,
                                            uint32_t* last = nullptr)
@@ -2060,6 +2063,7 @@ __device__ __forceinline__ void vlink_rows(VolLocalShared& sh, int r, int nr, in
     auto join = [&](uint32_t a, uint32_t b) {
         if (last) {
             const uint32_t pa = pk_id(lds_ld(sh.P + a)), pb = pk_id(lds_ld(sh.P + b));
+            if (!DIAG && pa == pb) return;
             const uint32_t pair = (pa << 16) | pb;
             if (pair == *last) return;
             *last = pair;
