@@ -642,6 +642,9 @@ def main():
     ap.add_argument("--profile-volume", type=int, default=0, metavar="ROUNDS",
                     help="only run ccl_label_3d on the 512^3 Bernoulli p = 0.3 volume, both "
                          "connectivities, ROUNDS times (for a kernel trace) and exit")
+    ap.add_argument("--profile-large", type=int, default=0, metavar="ROUNDS",
+                    help="only label the six 8192^2 8-connected images (Bernoulli 0.5 and the "
+                         "adversarial geometries) ROUNDS times (for a kernel trace) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel over MIB MiB (counter calibration)")
     ap.add_argument("--calibrate-segments", type=int, default=0, metavar="MIB",
@@ -725,6 +728,19 @@ def main():
                 ccl.label_3d(vol, conn, out=lab)
         torch.cuda.synchronize()
         log(f"[bench] profile-volume: {args.profile_volume} rounds")
+        return
+
+    if args.profile_large:
+        from paper_1712_09789_amd import workloads as wl
+        big = 8192
+        imgs = [torch.from_numpy(wl.make(kind, big, big, seed=0, **kw)).to(dev)
+                for kind, kw in (("bernoulli", {"p": 0.5}),) + wl.ADVERSARIAL]
+        lab = torch.empty((big, big), dtype=torch.int32, device=dev)
+        for _ in range(args.profile_large):
+            for img in imgs:
+                ccl.label(img, 8, out=lab)
+        torch.cuda.synchronize()
+        log(f"[bench] profile-large: {args.profile_large} rounds of {len(imgs)} images")
         return
 
     size = args.size
