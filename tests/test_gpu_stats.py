@@ -95,3 +95,50 @@ def test_empty_image_counts_zero(ccl):
     d = torch.zeros((0, 5), dtype=torch.uint8, device="cuda")
     labels, comps, count = ccl.label_stats(d, 8, capacity=4)
     assert int(count.item()) == 0
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_many_scan_blocks_closed_form(ccl, conn):
+    """An image with more scan blocks (1531) than the second scan level takes
+    in one pass (1024), so component numbers carry across its chunks: dashes
+    of three pixels with one-pixel gaps on every other row of 20000 x 20001
+    (50 million components; the last dash of a row is one pixel).  Every
+    label and every record field has a closed form, checked on the device."""
+    H, W = 20000, 20001
+    print(f"[stats] dashes {H}x{W} conn={conn}", flush=True)
+    x = torch.arange(W, device="cuda")
+    row = (x % 4 != 3).to(torch.uint8)
+    img = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    img[0::2] = row
+    ny, nd = (H + 1) // 2, (W + 3) // 4
+    n = ny * nd
+    labels, comps, count = ccl.label_stats(img, conn, capacity=n)
+    torch.cuda.synchronize()
+    assert int(count.item()) == n
+    y = torch.arange(0, H, 2, device="cuda", dtype=torch.int64)
+    want_row = torch.where(x % 4 != 3, (x // 4) * 4 + 1, 0)
+    assert torch.equal(labels[1::2], torch.zeros_like(labels[1::2]))
+    assert torch.equal(labels[0::2].long(),
+                       torch.where(want_row[None, :] > 0, y[:, None] * W + want_row[None, :], 0))
+    del labels
+    rec = comps[: n * 40].view(n, 40)
+    f32 = rec[:, :24].contiguous().view(torch.int32).view(n, 6).long()
+    f64 = rec[:, 24:].contiguous().view(torch.int64).view(n, 2)
+    k = torch.arange(nd, device="cuda", dtype=torch.int64)
+    x0 = 4 * k
+    area = torch.clamp(W - x0, max=3)
+    yy = y[:, None].expand(ny, nd).reshape(-1)
+    x0 = x0[None, :].expand(ny, nd).reshape(-1)
+    area = area[None, :].expand(ny, nd).reshape(-1)
+    want = {
+        "label": yy * W + x0 + 1, "area": area, "x_min": x0, "y_min": yy,
+        "x_max": x0 + area - 1, "y_max": yy,
+        "sum_x": area * x0 + area * (area - 1) // 2, "sum_y": yy * area,
+    }
+    got = {"label": f32[:, 0], "area": f32[:, 1], "x_min": f32[:, 2], "y_min": f32[:, 3],
+           "x_max": f32[:, 4], "y_max": f32[:, 5], "sum_x": f64[:, 0], "sum_y": f64[:, 1]}
+    for name in want:
+        if not torch.equal(got[name], want[name]):
+            bad = int(torch.nonzero(got[name] != want[name])[0])
+            raise AssertionError(f"conn={conn}: field {name} differs at component {bad}: "
+                                 f"got {int(got[name][bad])} want {int(want[name][bad])}")
