@@ -158,3 +158,29 @@ def test_every_corner_pattern_on_brick_corners(ccl, conn):
             bits = [(p >> b) & 1 for b in range(8)]
             vol[z - 1:z + 1, y - 1:y + 1, x - 1:x + 1] = np.array(bits, np.uint8).reshape(2, 2, 2)
         check(ccl, vol, conn, f"corner patterns {n0}")
+
+
+@pytest.mark.parametrize("case,conn", [("full", 26), ("full", 6), ("xplanes", 6), ("xplanes", 26)])
+def test_largest_volume_closed_forms(ccl, case, conn):
+    """A volume of 1290^3 voxels, just under the 2^31 - 1 the labels allow
+    (the largest positions the kernels compute): a full volume is one
+    component labelled 1; planes x = 0, 2, 4, ... are one component each,
+    labelled x + 1.  Checked on the device, slice block by slice block."""
+    n = 1290
+    assert n ** 3 < 2 ** 31 - 1
+    print(f"[volume] largest {case} {n}^3 conn={conn}", flush=True)
+    if case == "full":
+        vol = torch.ones((n, n, n), dtype=torch.uint8, device="cuda")
+    else:
+        vol = (torch.arange(n, device="cuda") % 2 == 0).to(torch.uint8).expand(n, n, n).contiguous()
+    out = ccl.label_3d(vol, conn)
+    torch.cuda.synchronize()
+    del vol
+    x = torch.arange(n, device="cuda", dtype=torch.int32)
+    want_row = torch.ones_like(x) if case == "full" else torch.where(x % 2 == 0, x + 1, 0)
+    for z0 in range(0, n, 64):
+        blk = out[z0:z0 + 64]
+        if not bool((blk == want_row).all()):
+            bad = torch.nonzero(blk != want_row)[0].tolist()
+            raise AssertionError(f"{case} conn={conn}: voxel (z,y,x)=({bad[0] + z0},{bad[1]},"
+                                 f"{bad[2]}) got {int(blk[tuple(bad)])}")
