@@ -349,6 +349,24 @@ def test_batch_uneven_mixed(ccl, seed):
         assert np.array_equal(outs2[j].cpu().numpy(), outs[i].cpu().numpy())
 
 
+def test_batch_thousands_of_small_images(ccl):
+    """3000 small images (sides 1 to 48, random density, both connectivities)
+    in one call: the image-of-tile, -group and -seam tables are long and
+    nearly every tile is an image of its own; every image against the
+    oracle."""
+    rng = np.random.default_rng(31)
+    imgs, conns = [], []
+    for i in range(3000):
+        H, W = (int(v) for v in rng.integers(1, 49, 2))
+        imgs.append(wl.bernoulli(H, W, float(rng.uniform(0.1, 0.9)), seed=i))
+        conns.append(int(rng.choice([4, 8])))
+    print(f"[parity] batch of {len(imgs)} small images", flush=True)
+    outs = ccl.label_batch([to_dev(im) for im in imgs], conns)
+    torch.cuda.synchronize()
+    for i, (im, c, o) in enumerate(zip(imgs, conns, outs)):
+        assert np.array_equal(o.cpu().numpy(), oracle_label(im, c)), (i, im.shape, c)
+
+
 @pytest.mark.parametrize("conn", [4, 8])
 def test_batch_c4_shapes(ccl, conn):
     """The batched workload (256 images, sides log-uniform in [64, 2048],
