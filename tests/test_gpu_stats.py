@@ -142,3 +142,22 @@ def test_many_scan_blocks_closed_form(ccl, conn):
             bad = int(torch.nonzero(got[name] != want[name])[0])
             raise AssertionError(f"conn={conn}: field {name} differs at component {bad}: "
                                  f"got {int(got[name][bad])} want {int(want[name][bad])}")
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_pitched_unaligned_view(ccl, conn):
+    """Statistics of a view into a wider image (row pitch > width, a first
+    pixel off any 16-byte boundary): every field equals the oracle's on the
+    same pixels."""
+    big = wl.bernoulli(700, 1031, 0.45, seed=77)
+    img = big[5:640, 14:900]
+    print(f"[stats] pitched view {img.shape} pitch {big.shape[1]} conn={conn}", flush=True)
+    d = torch.from_numpy(big).cuda()[5:640, 14:900]
+    assert d.stride(0) == big.shape[1] and d.data_ptr() % 16 != 0
+    labels, comps, count = ccl.label_stats(d, conn)
+    got = ccl.components_to_numpy(comps, count)
+    want = oracle_stats(np.ascontiguousarray(img), conn)
+    assert len(got) == len(want)
+    assert np.array_equal(labels.cpu().numpy(), oracle_label(np.ascontiguousarray(img), conn))
+    for f in want.dtype.names:
+        assert np.array_equal(got[f], want[f]), f
