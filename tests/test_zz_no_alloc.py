@@ -52,6 +52,26 @@ def test_noalloc_equals_label_on_two_calls(ccl):
     assert ccl.workspace_cached(st) == 0
 
 
+def test_noalloc_pitched_unaligned_view(ccl):
+    """A view into a wider image (row pitch > width, first pixel off a
+    16-byte boundary), after the calls above left their values in the shared
+    scratch: labels equal ccl_label's and the oracle's."""
+    big = wl.bernoulli(900, 1301, 0.55, seed=5)
+    d = torch.from_numpy(big).cuda()[3:850, 7:1290]
+    img = np.ascontiguousarray(big[3:850, 7:1290])
+    assert d.stride(0) == 1301 and d.data_ptr() % 16 != 0
+    for conn in (4, 8):
+        print(f"[noalloc] pitched view {img.shape} conn={conn}", flush=True)
+        want = ccl.label(d, conn)
+        torch.cuda.synchronize()
+        out = torch.full(img.shape, -1, dtype=torch.int32, device="cuda")
+        st = torch.cuda.current_stream()
+        assert noalloc(ccl, d, conn, out, st) == 0, ccl.lib().ccl_last_error()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want)
+        assert np.array_equal(out.cpu().numpy(), oracle_label(img, conn))
+
+
 def test_noalloc_rejects_images_beyond_the_scratch(ccl):
     d = torch.zeros((8192, 8192), dtype=torch.uint8, device="cuda")
     out = torch.full((8192, 8192), -7, dtype=torch.int32, device="cuda")
