@@ -43,3 +43,14 @@ def test_host_tensors_rejected():
         ccl.label(torch.zeros(8, 8, dtype=torch.uint8), 8)
     with pytest.raises(ValueError, match="device"):
         ccl.label_3d(torch.zeros(2, 8, 8, dtype=torch.uint8), 6)
+
+
+def test_inconsistent_count_raises():
+    """A negative component count is the device's report that a label could
+    not belong to its pixel: the records must not be handed out."""
+    comps = torch.zeros(4 * ccl.COMPONENT_DTYPE.itemsize, dtype=torch.uint8)
+    with pytest.raises(ccl.CCLError, match="consistency"):
+        ccl.components_to_numpy(comps, torch.tensor([-1], dtype=torch.int64))
+    # a valid count hands out that many records (fewer if the array is shorter)
+    assert len(ccl.components_to_numpy(comps, torch.tensor([3], dtype=torch.int64))) == 3
+    assert len(ccl.components_to_numpy(comps, torch.tensor([9], dtype=torch.int64))) == 4
